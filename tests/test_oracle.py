@@ -1,0 +1,278 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names the equation or closed form it rests on.  None of them
+re-types the oracle's own formula: the E-step is checked against the original
+V x V form (Eq. 2-3), the M-step against the argmax of the expected
+complete-data log-likelihood, the fixed point against the PPCA closed form
+(Tipping & Bishop 1999), the polar factor against the SVD, and whole fits
+against the t x t Gram form, planted truth and rotation equivariance.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from oracle import srm_oracle as so
+from paper_1608_04647_amd import synth
+
+
+def _rand_orth(rng, v, k):
+    q, _ = np.linalg.qr(rng.standard_normal((v, k)))
+    return q
+
+
+def _rand_spd(rng, k):
+    a = rng.standard_normal((k, k))
+    return a @ a.T / k + 0.5 * np.eye(k)
+
+
+def _tiny_state(seed, N=3, vs=(17, 23, 11), t=13, k=4):
+    rng = np.random.default_rng(seed)
+    Xh = [rng.standard_normal((v, t)) for v in vs[:N]]
+    Xh = [x - x.mean(axis=1, keepdims=True) for x in Xh]
+    W = [_rand_orth(rng, v, k) for v in vs[:N]]
+    rho2 = rng.uniform(0.3, 2.0, size=N)
+    Sig = _rand_spd(rng, k)
+    return Xh, W, rho2, Sig, t, k
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p1_estep_matches_naive_full_covariance(seed):
+    """Eq. 7-11 (reduced E-step) equal Eq. 2-3 with the full V x V Phi."""
+    Xh, W, rho2, Sig, t, k = _tiny_state(seed)
+    Y = sum((1.0 / r) * (w.T @ x) for w, r, x in zip(W, rho2, Xh))
+    S, M, rho0 = oracle.posterior(Y, rho2, Sig)
+    ES, Ess, ll_naive, cov = oracle.naive_estep(Xh, W, rho2, Sig)
+    assert np.allclose(S, ES, rtol=0, atol=1e-10 * np.abs(ES).max())
+    assert np.allclose(M, cov, rtol=0, atol=1e-10 * np.abs(cov).max())
+    Sig_new = M + S @ S.T / t  # Eq. 11 must equal (1/T) sum_t E[s s^T]
+    assert np.allclose(Sig_new, Ess / t, rtol=0, atol=1e-10 * np.abs(Ess).max())
+    c = [float(np.sum(x * x)) for x in Xh]
+    v = [x.shape[0] for x in Xh]
+    ll = oracle.loglik(c, v, t, rho2, Sig, Y, M, rho0)
+    assert abs(ll - ll_naive) <= 1e-10 * abs(ll_naive)
+
+
+def test_p1_loglik_matches_scipy_density():
+    """Log-likelihood (reading R9) equals scipy's multivariate normal log-pdf."""
+    from scipy.stats import multivariate_normal
+    Xh, W, rho2, Sig, t, k = _tiny_state(7)
+    Wst = np.vstack(W)
+    psi = np.concatenate([np.full(w.shape[0], r) for w, r in zip(W, rho2)])
+    Phi = Wst @ Sig @ Wst.T + np.diag(psi)
+    X = np.vstack(Xh)
+    ref = float(multivariate_normal(mean=np.zeros(X.shape[0]), cov=Phi).logpdf(X.T).sum())
+    Y = sum((1.0 / r) * (w.T @ x) for w, r, x in zip(W, rho2, Xh))
+    _, M, rho0 = oracle.posterior(Y, rho2, Sig)
+    c = [float(np.sum(x * x)) for x in Xh]
+    ll = oracle.loglik(c, [x.shape[0] for x in Xh], t, rho2, Sig, Y, M, rho0)
+    assert abs(ll - ref) <= 1e-10 * abs(ref)
+
+
+def test_p2_closed_form_mean():
+    """Sigma_s (I - rho0 M) = M with M = (Sigma_s^-1 + rho0 I)^-1 (algebra on Eq. 10)."""
+    rng = np.random.default_rng(3)
+    for k in (1, 3, 10, 40):
+        Sig = _rand_spd(rng, k)
+        rho2 = rng.uniform(0.2, 3.0, size=5)
+        Y = rng.standard_normal((k, 9))
+        S, M, rho0 = oracle.posterior(Y, rho2, Sig)
+        assert abs(rho0 - np.sum(1 / rho2)) < 1e-12 * rho0
+        assert np.allclose(M @ (np.linalg.inv(Sig) + rho0 * np.eye(k)), np.eye(k), atol=1e-10)
+        assert np.allclose(S, M @ Y, atol=1e-11 * np.abs(S).max())
+
+
+def test_p3_orthonormal_maps_after_fit():
+    """W_i^T W_i = I after every M-step (constraint of Sec. II-A)."""
+    w = synth.WORKLOADS["tiny"]
+    d = synth.generate(w, seed=0)
+    out = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    for Wi in out["W"]:
+        assert np.abs(Wi.T @ Wi - np.eye(w.k)).max() < 1e-12
+
+
+def test_p4_polar_equals_svd_and_is_procrustes_optimum():
+    """Eq. 4 A (A^T A)^-1/2 equals U V^T; tr(W^T A) is maximal over orthonormal W."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((60, 7)) @ np.diag(np.linspace(0.5, 4, 7))
+    W, tr = oracle.polar_svd(A)
+    lam, U = np.linalg.eigh(A.T @ A)
+    W2 = A @ (U / np.sqrt(lam)) @ U.T
+    assert np.abs(W - W2).max() < 1e-12
+    assert abs(tr - np.trace(W.T @ A)) < 1e-12 * tr
+    assert abs(tr - np.sum(np.linalg.svd(A, compute_uv=False))) < 1e-12 * tr
+    for _ in range(50):
+        Q = _rand_orth(rng, 60, 7)
+        assert np.trace(Q.T @ A) <= tr + 1e-12
+
+
+def test_p4_rank_deficient_raises():
+    """Reading R10: a rank-deficient A_i is an error, never a silent polar factor."""
+    A = np.zeros((20, 3))
+    A[:, 0] = 1.0
+    with pytest.raises(oracle.OracleRankError):
+        oracle.polar_svd(A)
+
+
+def test_p5_trace_identity():
+    """(1/T) sum_t tr E[s_t s_t^T] = tr(Sigma_s_new) (text after Eq. 11)."""
+    Xh, W, rho2, Sig, t, k = _tiny_state(5)
+    _, Ess, _, _ = oracle.naive_estep(Xh, W, rho2, Sig)
+    Y = sum((1.0 / r) * (w.T @ x) for w, r, x in zip(W, rho2, Xh))
+    S, M, _ = oracle.posterior(Y, rho2, Sig)
+    assert abs(np.trace(Ess) / t - np.trace(M + S @ S.T / t)) < 1e-12 * np.trace(Ess)
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", None), ("plain16", 0.02)])
+def test_p6_loglik_non_decreasing(name, scale):
+    """EM never lowers the likelihood (Sec. II-B: a constrained EM)."""
+    w = synth.WORKLOADS[name]
+    if scale is not None:
+        w = w.scaled(n_subjects=5, v_lo=int(w.v_lo * scale), v_hi=int(w.v_hi * scale),
+                     t=200, n_iter=12)
+    d = synth.generate(w, seed=1)
+    out = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"], final_loglik=True)
+    ll = out["ll"] + [out["ll_final"]]
+    for a, b in zip(ll[:-1], ll[1:]):
+        assert b >= a - 1e-10 * abs(a)
+    assert ll[-1] > ll[0]
+
+
+def _expected_complete_ll(Xh, W, rho2, Sig, ES, Ess):
+    """Q(W, rho, Sigma_s) of the EM: expected complete-data log-likelihood,
+    written from the model (Eq. 1) with the E-step moments."""
+    t = Xh[0].shape[1]
+    k = Sig.shape[0]
+    q = 0.0
+    for x, w, r in zip(Xh, W, rho2):
+        v = x.shape[0]
+        e = float(np.sum(x * x)) - 2.0 * float(np.sum((w.T @ x) * ES)) \
+            + float(np.trace(w.T @ w @ Ess))
+        q += -0.5 * t * v * math.log(r) - 0.5 * e / r
+    _, ld = np.linalg.slogdet(Sig)
+    q += -0.5 * t * ld - 0.5 * float(np.trace(np.linalg.solve(Sig, Ess)))
+    return q
+
+
+def test_p11_m_step_maximises_expected_complete_loglik():
+    """W (Eq. 4), rho^2 (reading R1) and Sigma_s (Eq. 6/11) maximise Q."""
+    Xh, W, rho2, Sig, t, k = _tiny_state(11)
+    ES, Ess, _, _ = oracle.naive_estep(Xh, W, rho2, Sig)
+    Sig_new = Ess / t
+    tau = float(np.trace(Sig_new))
+    newW, newr = [], []
+    for x in Xh:
+        c = float(np.sum(x * x))
+        wi, ri = oracle.m_step_subject(x, c, ES, tau)
+        newW.append(wi)
+        newr.append(ri)
+    newr = np.array(newr)
+    q0 = _expected_complete_ll(Xh, newW, newr, Sig_new, ES, Ess)
+    rng = np.random.default_rng(0)
+    for eps in (1e-2, 1e-4):
+        for i in range(len(Xh)):
+            Wp = list(newW)
+            Wp[i], _ = oracle.polar_svd(newW[i] + eps * rng.standard_normal(newW[i].shape))
+            assert _expected_complete_ll(Xh, Wp, newr, Sig_new, ES, Ess) < q0
+            for s in (1 + eps, 1 - eps):
+                rp = newr.copy()
+                rp[i] *= s
+                assert _expected_complete_ll(Xh, newW, rp, Sig_new, ES, Ess) < q0
+        D = rng.standard_normal((k, k))
+        Sp = Sig_new + eps * (D + D.T)
+        assert _expected_complete_ll(Xh, newW, newr, Sp, ES, Ess) < q0
+
+
+def test_p7_single_subject_reaches_ppca_closed_form():
+    """N = 1: SRM's covariance W Sigma_s W^T + rho^2 I with orthonormal W is the
+    PPCA model; its maximum (Tipping & Bishop 1999) is the top-k eigenspace of
+    the sample covariance, rho^2 = mean of the discarded eigenvalues and
+    eig(Sigma_s) = lambda_1..k - rho^2."""
+    rng = np.random.default_rng(8)
+    v, t, k = 30, 400, 3
+    Wt = _rand_orth(rng, v, k)
+    S = np.diag([3.0, 2.0, 1.4]) @ rng.standard_normal((k, t))
+    X = Wt @ S + 0.3 * rng.standard_normal((v, t)) + rng.standard_normal((v, 1))
+    W0 = _rand_orth(rng, v, k)
+    out = oracle.em_fit([X], k, 3000, [W0])
+    Xh = X - X.mean(axis=1, keepdims=True)
+    lam, U = np.linalg.eigh(Xh @ Xh.T / t)
+    lam, U = lam[::-1], U[:, ::-1]
+    rho2 = lam[k:].sum() / (v - k)
+    P_ref = U[:, :k] @ U[:, :k].T
+    W = out["W"][0]
+    assert np.linalg.norm(W @ W.T - P_ref) / math.sqrt(k) < 1e-8
+    assert abs(out["rho2"][0] - rho2) < 1e-8 * rho2
+    ev = np.sort(np.linalg.eigvalsh(out["Sigma_s"]))[::-1]
+    assert np.allclose(ev, lam[:k] - rho2, rtol=1e-7)
+
+
+def _procrustes_err(S_ref, S):
+    U, _, Vt = np.linalg.svd(S_ref @ S.T)
+    Q = U @ Vt
+    return np.linalg.norm(S_ref - Q @ S) / np.linalg.norm(S_ref)
+
+
+def _proj_err(W1, W2):
+    k = W1.shape[1]
+    return math.sqrt(2.0) * np.linalg.norm(W2 - W1 @ (W1.T @ W2)) / math.sqrt(k)
+
+
+def test_p8_planted_recovery_at_high_snr():
+    """Data drawn from the model (Eq. 1) at high SNR are recovered up to the
+    rotation the model cannot identify; error falls with the noise level.
+    Expected sizes (first-order): projector ~ sqrt(2) rho sqrt(v/t) / sigma_s,
+    S ~ rho / (sigma_s sqrt(N))."""
+    errs = []
+    for rho in (0.05, 0.2):
+        w = synth.Workload("hi-snr", 16, 100, 100, 2000, 5, 60,
+                           rho_lo=rho, rho_hi=rho)
+        d = synth.generate(w, seed=2, want_planted=True)
+        out = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+        g = d["globals"]
+        eS = _procrustes_err(g.S - g.S.mean(axis=1, keepdims=True), out["S"])
+        eW = max(_proj_err(a, b) for a, b in zip(d["W_planted"], out["W"]))
+        estW = math.sqrt(2) * rho * math.sqrt(100 / 2000)
+        estS = rho / math.sqrt(16)
+        assert eW < 3 * estW and eS < 3 * estS
+        errs.append((eW, eS))
+        assert np.allclose(out["rho2"], rho ** 2, rtol=0.1)
+    assert errs[0][0] < errs[1][0] and errs[0][1] < errs[1][1]
+
+
+def test_p9_rotation_equivariance():
+    """fit(W0 Q) = fit(W0) rotated: S -> Q^T S, Sigma_s -> Q^T Sigma_s Q,
+    W_i -> W_i Q, rho unchanged (structure of Eq. 4-11, Sigma_s start = I)."""
+    w = synth.WORKLOADS["tiny"]
+    d = synth.generate(w, seed=3)
+    rng = np.random.default_rng(9)
+    Q = _rand_orth(rng, w.k, w.k)
+    a = oracle.em_fit(d["X"], w.k, 6, d["W0"])
+    b = oracle.em_fit(d["X"], w.k, 6, [x @ Q for x in d["W0"]])
+    assert np.abs(b["S"] - Q.T @ a["S"]).max() < 1e-9 * np.abs(a["S"]).max()
+    assert np.abs(b["Sigma_s"] - Q.T @ a["Sigma_s"] @ Q).max() < 1e-9
+    assert np.allclose(a["rho2"], b["rho2"], rtol=1e-10)
+    for wa, wb in zip(a["W"], b["W"]):
+        assert np.abs(wb - wa @ Q).max() < 1e-9
+
+
+def test_p10_gram_form_agrees():
+    """The t x t Gram form (W^T Xhat = P S G, A^T A = S G S^T) is the same EM."""
+    w = synth.WORKLOADS["tiny"]
+    d = synth.generate(w, seed=4)
+    a = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    b = oracle.fit_gram(d["X"], w.k, w.n_iter, d["W0"])
+    assert np.abs(a["S"] - b["S"]).max() < 1e-10 * np.abs(a["S"]).max()
+    assert np.allclose(a["rho2"], b["rho2"], rtol=1e-10)
+    assert np.allclose(a["ll"], b["ll"], rtol=1e-12)
+    for wa, wb in zip(a["W"], b["W"]):
+        assert np.abs(wa - wb).max() < 1e-10
+
+
+def test_flop_model_counts():
+    """Sec. V-A flop model: two V x T x K products, one V x K x K product and an
+    economy SVD counted as Householder QR."""
+    f = oracle.flop_model([1000], 100, 10)
+    assert f == 2 * 2 * 1000 * 100 * 10 + 2 * 1000 * 100 + 2 * 1000 * 100 - 2 / 3 * 1000
