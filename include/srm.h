@@ -1,0 +1,166 @@
+/*
+ * srm.h -- C-ABI of the MI355X (gfx950) Shared Response Model EM library.
+ *
+ * The library fits the probabilistic Shared Response Model (SRM) of
+ * arXiv 1608.04647, Sec. II, with the distributed EM of Algorithm 1 (D-SRM):
+ *
+ *   model (Sec. II-A, Eq. 1):  x_it = W_i s_t + mu_i + eps_i,
+ *                              eps_i ~ N(0, rho_i^2 I), s_t ~ N(0, Sigma_s),
+ *                              W_i^T W_i = I,
+ *   E-step (Eq. 7-10):         Y = sum_i rho_i^-2 W_i^T Xhat_i,
+ *                              M = (Sigma_s^-1 + rho0 I)^-1, rho0 = sum rho_i^-2,
+ *                              S = E[S] = Sigma_s [I - rho0 M] Y,
+ *   M-step (Eq. 4, 5, 11):     Sigma_s = M + S S^T / t,
+ *                              A_i = Xhat_i S^T, W_i = A_i (A_i^T A_i)^-1/2,
+ *                              rho_i^2 = (||Xhat_i||^2 - 2 tr(W_i^T A_i)
+ *                                         + t tr(Sigma_s)) / (t v_i).
+ *
+ * The rho_i^2 update is the exact maximiser of the expected complete-data
+ * log-likelihood; the printed Eq. 5 is garbled (a missing 1/(T V) factor and
+ * the total V where v_i belongs).  The factor 1/2 printed in A_i is dropped
+ * (the polar factor is scale invariant).  Sigma_s starts at I, rho_i^2 at 1,
+ * and W_i at the caller's orthonormal W0_i.  The log-likelihood reported per
+ * iteration is the marginal Gaussian log-density of the demeaned data under
+ * the parameters entering that iteration, reduced with the inversion lemma
+ * (Eq. 7) and Eq. 8.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns srm_status; no C++ exception crosses the ABI.
+ *    On failure, srm_last_error() returns a message (per thread).
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary process memory.
+ *  - The library never allocates device memory: everything it keeps lives in
+ *    the caller's workspace (see srm_workspace_size), which must stay valid
+ *    and untouched until srm_free().
+ *  - All device work is enqueued on desc.hip_stream (a hipStream_t; NULL means
+ *    the library creates its own non-blocking stream).  Calls that return host
+ *    values synchronise that stream; the others only enqueue.
+ *  - Matrices are row-major.  X_i is v_i x t (voxels x TRs) with row stride t.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef SRM_H_
+#define SRM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srm_ctx srm_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  SRM_OK = 0,
+  SRM_E_ARG = 1,       /* invalid argument (sizes, NULL pointers, precision)   */
+  SRM_E_WORKSPACE = 2, /* workspace NULL, misaligned or smaller than required */
+  SRM_E_HIP = 3,       /* a HIP runtime call failed                            */
+  SRM_E_RANK = 4,      /* A_i^T A_i numerically singular: lambda_min <= 1e-13 lambda_max */
+  SRM_E_NOTPD = 5,     /* Sigma_s or Sigma_s^-1 + rho0 I not positive definite */
+  SRM_E_NONFINITE = 6, /* NaN or Inf in the input data                         */
+  SRM_E_STATE = 7      /* call not valid in the context's current state        */
+} srm_status;
+
+/* Storage format of the demeaned data Xhat_i inside the workspace.
+ * SRM_FP32:   float32, FP32 matrix-core products.
+ * SRM_BF16:   one bfloat16 per element; W_i and S enter as bf16 hi+lo pairs
+ *             (2 bf16 products per multiply, FP32 accumulation).
+ * SRM_BF16X2: Xhat_i = hi + lo, both bfloat16 (3 bf16 products per multiply,
+ *             the lo*lo term dropped, FP32 accumulation).
+ * The k x k steps (Cholesky, Jacobi eigensolver, polar factor, rho_i^2) and
+ * the cross-subject reductions run in FP64 in every format.               */
+typedef enum { SRM_FP32 = 0, SRM_BF16 = 1, SRM_BF16X2 = 2 } srm_prec;
+
+enum {
+  SRM_NO_GRAPH = 1u,    /* launch each iteration's kernels directly instead of
+                           replaying one captured hipGraph                     */
+  SRM_NO_W0_CHECK = 2u, /* skip the host check that W0_i^T W0_i = I            */
+  SRM_TWO_PASS = 4u     /* force two passes over Xhat per iteration even where a
+                           one-pass sweep is available                         */
+};
+
+typedef struct {
+  int32_t n_subjects;   /* N >= 1                                              */
+  const int64_t *v;     /* host [N]: voxels per subject, k <= v_i < 2^31       */
+  int64_t t;            /* TRs (samples), 2 <= t <= 65536, k <= t              */
+  int32_t k;            /* shared features, 1 <= k <= 128                      */
+  srm_prec prec;        /* storage format of Xhat                              */
+  uint32_t flags;       /* SRM_* flags above                                   */
+  void *hip_stream;     /* hipStream_t or NULL                                 */
+} srm_desc;
+
+/* Bytes of device workspace srm_init needs for this problem (Sec. II-C, II-D:
+ * the E-step keeps only k x k and k x t state beside the data).  Returns
+ * SRM_E_ARG for an invalid descriptor. */
+srm_status srm_workspace_size(const srm_desc *desc, size_t *bytes);
+
+/* Algorithm 1, initialisation: demean each X_i (mu_i = row means over t),
+ * store Xhat_i in desc->prec inside the workspace, compute c_i = ||Xhat_i||^2
+ * from the stored values, set W_i = W0_i, rho_i^2 = 1, Sigma_s = I, and run
+ * the first E-step (its log-likelihood is the first one srm_fit reports).
+ *   X:  host array of N device pointers; X[i] is v_i x t float32, row stride t.
+ *       Read during the call only (the caller keeps ownership).
+ *   W0: host array of N host pointers; W0[i] is v_i x k float64 with
+ *       orthonormal columns (checked: max|W0^T W0 - I| <= 1e-8 unless
+ *       SRM_NO_W0_CHECK).  Read during the call only.
+ *   workspace: device memory of at least srm_workspace_size bytes, 256-byte
+ *       aligned, owned by the caller, used exclusively by this context.
+ * Errors: SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_NONFINITE, SRM_E_HIP, SRM_E_NOTPD.
+ * On success *out is a new context (free with srm_free). */
+srm_status srm_init(srm_ctx **out, const srm_desc *desc, const float *const *X,
+                    const double *const *W0, void *workspace, size_t ws_bytes);
+
+/* One EM iteration of Algorithm 1 (M-step on the current posterior, then the
+ * next E-step).  loglik (host, nullable) receives the log-likelihood of the
+ * parameters entering the iteration.  Synchronises the stream.
+ * Errors: SRM_E_RANK, SRM_E_NOTPD, SRM_E_HIP. */
+srm_status srm_em_step(srm_ctx *ctx, double *loglik);
+
+/* n_iter >= 0 EM iterations (fixed count; the paper's stopping criterion is
+ * unspecified).  loglik (host [n_iter], nullable) receives the log-likelihood
+ * of the parameters entering each iteration.  The iterations are enqueued
+ * without host synchronisation; the stream is synchronised once at the end. */
+srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
+
+/* Project new samples of subject i into the shared space (Sec. II-A:
+ * s = W_i^T (x - mu_i)):  S_out = W_i^T (X_new - mu_i 1^T).
+ *   X_new: device, v_i x t_new float32, row stride t_new (t_new >= 1).
+ *   S_out: device, k x t_new float32, row stride t_new.
+ * Valid after at least one iteration (SRM_E_STATE otherwise).  Enqueues only. */
+srm_status srm_transform(srm_ctx *ctx, int32_t i, const float *X_new,
+                         int64_t t_new, float *S_out);
+
+/* Results of the last completed iteration (SRM_E_STATE before the first).
+ *  srm_get_w:      device dst, v_i x k float32: W_i (orthonormal columns).
+ *  srm_get_s:      device dst, k x t float32: the shared response E[S] of the
+ *                  E-step the final W_i were built from.
+ *  srm_get_rho2:   host dst [N] float64.
+ *  srm_get_sigma_s:host dst k x k float64.
+ *  srm_get_mu:     device dst, v_i float64: subject i's voxel means.
+ *  srm_get_loglik: host dst [capacity] float64, all log-likelihoods computed so
+ *                  far (n_iter + 1 after n_iter iterations: the last one is the
+ *                  log-likelihood of the final parameters); *count receives
+ *                  their number (dst may be NULL to query it).
+ * The host getters synchronise the stream. */
+srm_status srm_get_w(srm_ctx *ctx, int32_t i, float *dst);
+srm_status srm_get_s(srm_ctx *ctx, float *dst);
+srm_status srm_get_rho2(srm_ctx *ctx, double *dst);
+srm_status srm_get_sigma_s(srm_ctx *ctx, double *dst);
+srm_status srm_get_mu(srm_ctx *ctx, int32_t i, double *dst);
+srm_status srm_get_loglik(srm_ctx *ctx, double *dst, int32_t capacity,
+                          int32_t *count);
+
+/* Number of completed iterations. */
+srm_status srm_iterations(const srm_ctx *ctx, int32_t *n);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *srm_last_error(void);
+
+/* Frees the context (not the caller's workspace).  NULL is ignored. */
+void srm_free(srm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRM_H_ */

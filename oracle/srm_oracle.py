@@ -133,9 +133,12 @@ def m_step_subject(Xh: np.ndarray, c: float, S: np.ndarray, tau: float):
 
 
 def em_fit(X: List[np.ndarray], k: int, n_iter: int, W0: List[np.ndarray],
-           final_loglik: bool = False, record: bool = False):
+           final_loglik: bool = False, record: bool = False,
+           demeaned: bool = False):
     """Algorithm 1 (D-SRM) run serially: n_iter EM iterations from W0.
 
+    With demeaned=True the X_i are taken as the already demeaned Xhat_i (used
+    to feed the oracle exactly the values a reduced-precision store holds).
     Returns a dict with W (list), S, rho2, Sigma_s, mu, c and ll (the
     log-likelihood of the parameters entering each iteration; with
     final_loglik, one more value for the parameters leaving the last one)."""
@@ -143,7 +146,11 @@ def em_fit(X: List[np.ndarray], k: int, n_iter: int, W0: List[np.ndarray],
     t = X[0].shape[1]
     mus, Xh, c = [], [], []
     for Xi in X:  # initialisation: demean per subject
-        m, xh, ci = demean(Xi)
+        if demeaned:
+            xh = np.asarray(Xi, dtype=np.float64)
+            m, ci = np.zeros(xh.shape[0]), float(np.sum(xh * xh))
+        else:
+            m, xh, ci = demean(Xi)
         mus.append(m)
         Xh.append(xh)
         c.append(ci)

@@ -1,0 +1,738 @@
+// Host side of the SRM C-ABI: argument validation, work planning, workspace
+// layout, W0 upload, kernel sequencing and hipGraph replay of one iteration.
+// The EM arithmetic itself runs in the kernels of srm_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/srm.h"
+#include "srm_internal.h"
+
+namespace srm {
+hipError_t launch_convert(hipStream_t, int, const ConvertArgs&);
+hipError_t launch_rowsum(hipStream_t, int, const double*, const Subject*, double*);
+hipError_t launch_mphase(hipStream_t, int, int, int, const MArgs&);
+hipError_t launch_ephase(hipStream_t, int, int, int, const EArgs&);
+hipError_t launch_ereduce(hipStream_t, int, int, int, const RArgs&);
+int ereduce_ct(int kp);
+hipError_t launch_post_prep(hipStream_t, int, const PrepArgs&);
+hipError_t launch_post_s(hipStream_t, int, int, int, const SArgs&);
+hipError_t launch_post_fin(hipStream_t, int, const FinArgs&);
+hipError_t launch_copy_state(hipStream_t, const CopyArgs&);
+hipError_t launch_polar(hipStream_t, int, int, const QArgs&);
+hipError_t launch_get_w(hipStream_t, int, const WArgs&);
+hipError_t launch_transform(hipStream_t, int, int, const TArgs&, const TFArgs&);
+hipError_t occupancy_mphase(int, int, int*);
+hipError_t occupancy_ephase(int, int, int*);
+}  // namespace srm
+
+using namespace srm;
+
+namespace {
+
+thread_local std::string g_err;
+
+srm_status fail(srm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_OR_FAIL(expr)                                                 \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return fail(SRM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Target number of E-phase workgroups: one full residency round on 256 CUs
+// (two 4-wave workgroups per CU).  Fixed so that the workspace size does not
+// depend on a device query.
+constexpr int kEphaseWGs = 512;
+constexpr int kReduceWGs = 512;
+
+struct Plan {
+  int N = 0, k = 0, KP = 0, NB = 0, prec = 0;
+  int64_t t = 0, ldt = 0, total_rows = 0;
+  int npanel = 0, nranges = 0, nslices = 0;
+  int rct = 0, ncol_r = 0, gsub = 0, ngrp = 0;
+  int nblk_s = 0;
+  std::vector<Subject> subj;
+  std::vector<Slice> slices;
+  std::vector<int32_t> range_slice;
+  // workspace offsets (bytes)
+  size_t o_xh = 0, o_xl = 0, o_mu = 0, o_rowc = 0, o_c = 0, o_arec = 0,
+         o_zpart = 0, o_gpart = 0, o_p64 = 0, o_rho2 = 0, o_ygrp = 0,
+         o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
+         o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
+         o_prepwork = 0, o_polwork = 0, o_sc = 0, o_ll = 0, o_subj = 0,
+         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0;
+  size_t total = 0;
+  size_t arec_bytes = 0, srec_bytes = 0, zpart_bytes = 0;
+};
+
+size_t esz_x(int prec) { return prec == SRM_FP32 ? 4 : 2; }
+
+srm_status validate(const srm_desc* d) {
+  if (!d) return fail(SRM_E_ARG, "desc is NULL");
+  if (d->n_subjects < 1) return fail(SRM_E_ARG, "n_subjects must be >= 1");
+  if (!d->v) return fail(SRM_E_ARG, "v is NULL");
+  if (d->k < 1 || d->k > kMaxK)
+    return fail(SRM_E_ARG, "k=%d outside [1, %d]", d->k, kMaxK);
+  if (d->t < 2 || d->t > 65536)
+    return fail(SRM_E_ARG, "t=%lld outside [2, 65536]", (long long)d->t);
+  if (d->k > d->t) return fail(SRM_E_ARG, "k=%d exceeds t=%lld", d->k, (long long)d->t);
+  if (d->prec != SRM_FP32 && d->prec != SRM_BF16 && d->prec != SRM_BF16X2)
+    return fail(SRM_E_ARG, "unknown precision %d", (int)d->prec);
+  for (int i = 0; i < d->n_subjects; ++i) {
+    if (d->v[i] < d->k)
+      return fail(SRM_E_ARG, "v[%d]=%lld is below k=%d", i, (long long)d->v[i], d->k);
+    if (d->v[i] >= (int64_t)1 << 31)
+      return fail(SRM_E_ARG, "v[%d]=%lld too large", i, (long long)d->v[i]);
+  }
+  return SRM_OK;
+}
+
+srm_status make_plan(const srm_desc* d, Plan& p) {
+  srm_status s = validate(d);
+  if (s != SRM_OK) return s;
+  p.N = d->n_subjects;
+  p.k = d->k;
+  p.KP = (int)round_up(d->k, 16);
+  p.NB = p.KP / 16;
+  p.prec = d->prec;
+  p.t = d->t;
+  p.ldt = round_up(d->t, kColPad);
+  p.subj.resize(p.N);
+  int64_t row = 0;
+  for (int i = 0; i < p.N; ++i) {
+    p.subj[i].row0 = row;
+    p.subj[i].v = (int32_t)d->v[i];
+    p.subj[i].vp = (int32_t)round_up(d->v[i], kRowPad);
+    row += p.subj[i].vp;
+  }
+  p.total_rows = row;
+  // E-phase: equal row ranges (multiples of 32 rows) split at subject ends.
+  p.npanel = (int)((p.ldt + 255) / 256);
+  const int64_t nblk32 = p.total_rows / 32;
+  p.nranges = (int)std::max<int64_t>(1, std::min<int64_t>(nblk32, kEphaseWGs / p.npanel));
+  p.range_slice.assign(p.nranges + 1, 0);
+  p.slices.clear();
+  int si = 0;
+  for (int r = 0; r < p.nranges; ++r) {
+    int64_t b0 = nblk32 * r / p.nranges, b1 = nblk32 * (r + 1) / p.nranges;
+    p.range_slice[r] = (int32_t)p.slices.size();
+    int64_t r0 = b0 * 32;
+    const int64_t r1 = b1 * 32;
+    while (r0 < r1) {
+      while (p.subj[si].row0 + p.subj[si].vp <= r0) ++si;
+      const int64_t se = std::min<int64_t>(r1, p.subj[si].row0 + p.subj[si].vp);
+      Slice sl;
+      sl.row0 = r0;
+      sl.nrows = (int32_t)(se - r0);
+      sl.subj = si;
+      p.slices.push_back(sl);
+      r0 = se;
+    }
+  }
+  p.range_slice[p.nranges] = (int32_t)p.slices.size();
+  p.nslices = (int)p.slices.size();
+  for (auto& su : p.subj) { su.s_beg = 0; su.s_end = 0; }
+  for (int s = p.nslices - 1; s >= 0; --s) p.subj[p.slices[s].subj].s_beg = s;
+  for (int s = 0; s < p.nslices; ++s) p.subj[p.slices[s].subj].s_end = s + 1;
+  // reduction geometry
+  p.rct = ereduce_ct(p.KP);
+  p.ncol_r = (int)(p.ldt / p.rct);
+  p.ngrp = std::max(1, std::min(p.N, kReduceWGs / p.ncol_r));
+  p.gsub = (p.N + p.ngrp - 1) / p.ngrp;
+  p.ngrp = (p.N + p.gsub - 1) / p.gsub;
+  p.nblk_s = (int)(p.ldt / 16);
+
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (size_t)round_up((int64_t)(off + bytes), 256);
+    return o;
+  };
+  const size_t xplane = (size_t)p.total_rows * p.ldt * esz_x(p.prec);
+  p.o_xh = take(xplane);
+  p.o_xl = p.prec == SRM_BF16X2 ? take(xplane) : p.o_xh;
+  p.o_mu = take(sizeof(double) * p.total_rows);
+  p.o_rowc = take(sizeof(double) * p.total_rows);
+  p.o_c = take(sizeof(double) * p.N);
+  p.arec_bytes = (size_t)p.total_rows * p.KP * 4;  // FP32, or 2 bf16 planes
+  p.o_arec = take(p.arec_bytes);
+  p.zpart_bytes = (size_t)p.nslices * p.KP * p.ldt * 4;
+  p.o_zpart = take(p.zpart_bytes);
+  p.o_gpart = take((size_t)p.nslices * p.KP * p.KP * 4);
+  p.o_p64 = take((size_t)p.N * p.KP * p.KP * 8);
+  p.o_rho2 = take(sizeof(double) * p.N);
+  p.o_ygrp = take((size_t)p.ngrp * p.KP * p.ldt * 8);
+  p.o_s64cur = take((size_t)p.KP * p.ldt * 8);
+  p.o_s64new = take((size_t)p.KP * p.ldt * 8);
+  p.srec_bytes = (size_t)p.KP * p.ldt * 4;
+  p.o_sreccur = take(p.srec_bytes);
+  p.o_srecnew = take(p.srec_bytes);
+  p.o_sspart = take((size_t)p.nblk_s * p.KP * p.KP * 8);
+  p.o_trpart = take((size_t)p.nblk_s * 8);
+  p.o_sigcur = take((size_t)p.KP * p.KP * 8);
+  p.o_signew = take((size_t)p.KP * p.KP * 8);
+  p.o_M = take((size_t)p.KP * p.KP * 8);
+  p.o_prepwork = take((size_t)2 * p.KP * (p.KP + 1) * 8);
+  p.o_polwork = take(p.KP > 96 ? (size_t)p.N * 2 * p.KP * (p.KP + 1) * 8 : 8);
+  p.o_sc = take(sizeof(Scalars));
+  p.o_ll = take(sizeof(double) * kLLCapacity);
+  p.o_subj = take(sizeof(Subject) * p.N);
+  p.o_slices = take(sizeof(Slice) * p.nslices);
+  p.o_rs = take(sizeof(int32_t) * (p.nranges + 1));
+  p.o_srow0 = take(sizeof(int64_t) * p.N);
+  p.o_sv = take(sizeof(int32_t) * p.N);
+  p.o_xptr = take(sizeof(void*) * p.N);
+  p.total = off;
+  return SRM_OK;
+}
+
+}  // namespace
+
+struct srm_ctx {
+  Plan p;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  int m_grid = 0;
+  int64_t m_tpw = 0, m_ntiles = 0;
+  int iters = 0;
+  bool graph_ok = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+// A-record index of element (global row R, feature b).
+inline size_t arec_index(int NB, int64_t R, int b) {
+  const int64_t rb = R >> 5;
+  const int rr = (int)(R & 31);
+  const int g = (rr & 15) >> 2, e = ((rr >> 4) << 2) + (rr & 3);
+  const int lane = (b & 15) + 16 * g;
+  return (size_t)(((rb * NB + (b >> 4)) * 64 + lane) * 8 + e);
+}
+
+inline uint16_t host_f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+inline float host_bf2f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int n_threads() {
+  unsigned n = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, n ? n : 1u));
+}
+
+template <class F>
+void parallel_for(int n, F f) {
+  const int nt = std::min(n, n_threads());
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w] { for (int i = w; i < n; i += nt) f(i); });
+  for (auto& x : th) x.join();
+}
+
+srm_status check_w0(const Plan& p, const double* const* W0) {
+  std::vector<double> err(p.N, 0.0);
+  parallel_for(p.N, [&](int i) {
+    const int v = p.subj[i].v, k = p.k;
+    std::vector<double> g((size_t)k * k, 0.0);
+    const double* w = W0[i];
+    for (int r = 0; r < v; ++r) {
+      const double* row = w + (size_t)r * k;
+      for (int a = 0; a < k; ++a) {
+        const double x = row[a];
+        double* ga = g.data() + (size_t)a * k;
+        for (int b = a; b < k; ++b) ga[b] += x * row[b];
+      }
+    }
+    double m = 0.0;
+    for (int a = 0; a < k; ++a)
+      for (int b = a; b < k; ++b)
+        m = std::max(m, std::fabs(g[(size_t)a * k + b] - (a == b ? 1.0 : 0.0)));
+    err[i] = m;
+  });
+  for (int i = 0; i < p.N; ++i)
+    if (!(err[i] <= 1e-8))
+      return fail(SRM_E_ARG, "W0[%d] is not orthonormal (max|W^T W - I| = %g)", i, err[i]);
+  return SRM_OK;
+}
+
+// W0 -> A records (A = W0, deferred polar factor P = I) and upload.
+srm_status upload_w0(srm_ctx* c, const double* const* W0) {
+  const Plan& p = c->p;
+  std::vector<srm_status> st(p.N, SRM_OK);
+  std::vector<std::string> msg(p.N);
+  const int nt = std::min(p.N, n_threads());
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w) {
+    th.emplace_back([&, w] {
+      std::vector<char> buf;
+      for (int i = w; i < p.N; i += nt) {
+        const Subject& su = p.subj[i];
+        const size_t nrec_el = (size_t)su.vp * p.KP;  // elements in its records
+        const size_t base = arec_index(p.NB, su.row0, 0);
+        if (p.prec == SRM_FP32) {
+          buf.assign(nrec_el * 4, 0);
+          float* f = reinterpret_cast<float*>(buf.data());
+          for (int r = 0; r < su.v; ++r)
+            for (int b = 0; b < p.k; ++b)
+              f[arec_index(p.NB, su.row0 + r, b) - base] = (float)W0[i][(size_t)r * p.k + b];
+          if (hipMemcpy(c->ws + p.o_arec + base * 4, buf.data(), nrec_el * 4,
+                        hipMemcpyHostToDevice) != hipSuccess)
+            st[i] = SRM_E_HIP;
+        } else {
+          buf.assign(nrec_el * 4, 0);
+          uint16_t* hi = reinterpret_cast<uint16_t*>(buf.data());
+          uint16_t* lo = hi + nrec_el;
+          for (int r = 0; r < su.v; ++r)
+            for (int b = 0; b < p.k; ++b) {
+              const float f = (float)W0[i][(size_t)r * p.k + b];
+              const uint16_t h = host_f2bf(f);
+              const size_t o = arec_index(p.NB, su.row0 + r, b) - base;
+              hi[o] = h;
+              lo[o] = host_f2bf(f - host_bf2f(h));
+            }
+          const size_t plane = p.arec_bytes / 2;
+          if (hipMemcpy(c->ws + p.o_arec + base * 2, hi, nrec_el * 2,
+                        hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(c->ws + p.o_arec + plane + base * 2, lo, nrec_el * 2,
+                        hipMemcpyHostToDevice) != hipSuccess)
+            st[i] = SRM_E_HIP;
+        }
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (int i = 0; i < p.N; ++i)
+    if (st[i] != SRM_OK) return fail(st[i], "upload of W0[%d] failed", i);
+  return SRM_OK;
+}
+
+struct Ptrs {
+  void *xh, *xl, *ah, *al, *shc, *slc, *shn, *sln;
+};
+
+Ptrs ptrs(const srm_ctx* c) {
+  const Plan& p = c->p;
+  Ptrs q;
+  q.xh = c->ws + p.o_xh;
+  q.xl = c->ws + p.o_xl;
+  q.ah = c->ws + p.o_arec;
+  q.al = c->ws + p.o_arec + (p.prec == SRM_FP32 ? 0 : p.arec_bytes / 2);
+  q.shc = c->ws + p.o_sreccur;
+  q.slc = c->ws + p.o_sreccur + p.srec_bytes / 2;
+  q.shn = c->ws + p.o_srecnew;
+  q.sln = c->ws + p.o_srecnew + p.srec_bytes / 2;
+  return q;
+}
+
+// E-phase + reduction + posterior: from the current A, P, rho produce the
+// E-step's S (into the "new" buffers), Sigma_s_new, tau_new and one LL.
+hipError_t enqueue_estep(srm_ctx* c, bool with_polar) {
+  const Plan& p = c->p;
+  const Ptrs q = ptrs(c);
+  hipStream_t st = c->stream;
+  hipError_t e;
+  EArgs ea{q.xh, q.xl, q.ah, q.al, c->at<Slice>(p.o_slices),
+           c->at<int32_t>(p.o_rs), c->at<float>(p.o_zpart), c->at<float>(p.o_gpart),
+           p.ldt, p.npanel, with_polar ? 1 : 0};
+  if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
+  if (with_polar) {
+    QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_c),
+             c->at<double>(p.o_rho2), c->at<double>(p.o_p64), c->at<double>(p.o_polwork),
+             c->at<Scalars>(p.o_sc), p.k, p.t};
+    if ((e = launch_polar(st, p.KP, p.N, qa)) != hipSuccess) return e;
+  }
+  RArgs ra{c->at<float>(p.o_zpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_p64),
+           c->at<double>(p.o_rho2), c->at<double>(p.o_ygrp), p.N, p.gsub, p.ldt};
+  if ((e = launch_ereduce(st, p.KP, p.ncol_r, p.ngrp, ra)) != hipSuccess) return e;
+  PrepArgs pa{c->at<double>(p.o_rho2), c->at<double>(p.o_c), c->at<Subject>(p.o_subj),
+              c->at<double>(p.o_sigcur), c->at<double>(p.o_M), c->at<double>(p.o_prepwork),
+              c->at<Scalars>(p.o_sc), p.N, p.k};
+  if ((e = launch_post_prep(st, p.KP, pa)) != hipSuccess) return e;
+  SArgs sa{c->at<double>(p.o_ygrp), c->at<double>(p.o_M), c->at<double>(p.o_s64new),
+           q.shn, q.sln, c->at<double>(p.o_sspart), c->at<double>(p.o_trpart),
+           p.ngrp, p.k, p.t, p.ldt};
+  if ((e = launch_post_s(st, p.KP, p.prec, p.nblk_s, sa)) != hipSuccess) return e;
+  double Vtot = 0.0;
+  for (const auto& su : p.subj) Vtot += su.v;
+  FinArgs fa{c->at<double>(p.o_sspart), c->at<double>(p.o_trpart), c->at<double>(p.o_M),
+             c->at<double>(p.o_signew), c->at<double>(p.o_ll), c->at<Scalars>(p.o_sc),
+             p.nblk_s, p.k, p.t, Vtot};
+  return launch_post_fin(st, p.KP, fa);
+}
+
+// One EM iteration: M-step on the current posterior, then the next E-step.
+hipError_t enqueue_iteration(srm_ctx* c) {
+  const Plan& p = c->p;
+  const Ptrs q = ptrs(c);
+  hipStream_t st = c->stream;
+  hipError_t e;
+  CopyArgs ca{c->at<double>(p.o_s64new), c->at<double>(p.o_s64cur),
+              c->at<uint4>(p.o_srecnew), c->at<uint4>(p.o_sreccur),
+              c->at<double>(p.o_signew), c->at<double>(p.o_sigcur), c->at<Scalars>(p.o_sc),
+              (int64_t)p.KP * p.ldt, (int64_t)(p.srec_bytes / 16), p.KP * p.KP};
+  if ((e = launch_copy_state(st, ca)) != hipSuccess) return e;
+  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, p.total_rows, c->m_ntiles, c->m_tpw};
+  if ((e = launch_mphase(st, p.KP, p.prec, c->m_grid, ma)) != hipSuccess) return e;
+  return enqueue_estep(c, true);
+}
+
+srm_status run_iterations(srm_ctx* c, int n) {
+  for (int it = 0; it < n; ++it) {
+    if (!(c->flags & SRM_NO_GRAPH) && !c->graph_ok && c->gexec == nullptr) {
+      // Capture one iteration once; fall back to direct launches on failure.
+      hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = enqueue_iteration(c);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(c->stream, &g);
+        if (e2 == hipSuccess && e3 == hipSuccess && g) {
+          if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) == hipSuccess) {
+            c->graph = g;
+            c->graph_ok = true;
+          } else {
+            (void)hipGraphDestroy(g);
+            c->gexec = nullptr;
+          }
+        } else if (g) {
+          (void)hipGraphDestroy(g);
+        }
+      }
+      (void)hipGetLastError();
+      if (!c->graph_ok) c->flags |= SRM_NO_GRAPH;
+    }
+    if (c->graph_ok) {
+      HIP_OR_FAIL(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      HIP_OR_FAIL(enqueue_iteration(c));
+    }
+    ++c->iters;
+  }
+  return SRM_OK;
+}
+
+srm_status read_scalars(srm_ctx* c, Scalars* s) {
+  HIP_OR_FAIL(hipMemcpyAsync(s, c->ws + c->p.o_sc, sizeof(Scalars),
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  if (s->status == SRM_E_RANK)
+    return fail(SRM_E_RANK, "A_i^T A_i is numerically singular for some subject");
+  if (s->status == SRM_E_NOTPD)
+    return fail(SRM_E_NOTPD, "Sigma_s or Sigma_s^-1 + rho0 I is not positive definite");
+  if (s->status != 0) return fail((srm_status)s->status, "device error %d", s->status);
+  return SRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+srm_status srm_workspace_size(const srm_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(SRM_E_ARG, "bytes is NULL");
+  Plan p;
+  srm_status s = make_plan(desc, p);
+  if (s != SRM_OK) return s;
+  *bytes = p.total;
+  return SRM_OK;
+}
+
+srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
+                    const double* const* W0, void* workspace, size_t ws_bytes) {
+  if (!out) return fail(SRM_E_ARG, "out is NULL");
+  *out = nullptr;
+  Plan p;
+  srm_status s = make_plan(desc, p);
+  if (s != SRM_OK) return s;
+  if (!X) return fail(SRM_E_ARG, "X is NULL");
+  if (!W0) return fail(SRM_E_ARG, "W0 is NULL");
+  for (int i = 0; i < p.N; ++i) {
+    if (!X[i]) return fail(SRM_E_ARG, "X[%d] is NULL", i);
+    if (!W0[i]) return fail(SRM_E_ARG, "W0[%d] is NULL", i);
+  }
+  if (!workspace) return fail(SRM_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(SRM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.total)
+    return fail(SRM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, p.total);
+  if (!(desc->flags & SRM_NO_W0_CHECK)) {
+    s = check_w0(p, W0);
+    if (s != SRM_OK) return s;
+  }
+
+  srm_ctx* c = new srm_ctx();
+  c->p = std::move(p);
+  c->flags = desc->flags;
+  c->ws = static_cast<char*>(workspace);
+  const Plan& P = c->p;
+  if (desc->hip_stream) {
+    c->stream = static_cast<hipStream_t>(desc->hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(SRM_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    c->own_stream = true;
+  }
+  auto bail = [&](srm_status st) {
+    srm_free(c);
+    return st;
+  };
+
+  // M-phase grid: one residency round of equal contiguous tile ranges.
+  int occ = 0;
+  if (occupancy_mphase(P.KP, P.prec, &occ) != hipSuccess || occ < 1) occ = 1;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      ncu = prop.multiProcessorCount;
+  }
+  c->m_ntiles = (P.total_rows + 63) / 64;
+  const int64_t want = (int64_t)occ * ncu;
+  c->m_tpw = std::max<int64_t>(1, (c->m_ntiles + want - 1) / want);
+  c->m_grid = (int)((c->m_ntiles + c->m_tpw - 1) / c->m_tpw);
+
+  // Host tables.
+  std::vector<int64_t> srow0(P.N);
+  std::vector<int32_t> sv(P.N);
+  for (int i = 0; i < P.N; ++i) {
+    srow0[i] = P.subj[i].row0;
+    sv[i] = P.subj[i].v;
+  }
+  Scalars sc{};
+  std::vector<double> ones(P.N, 1.0);
+  std::vector<double> eyeKP((size_t)P.KP * P.KP, 0.0);
+  for (int j = 0; j < P.k; ++j) eyeKP[(size_t)j * P.KP + j] = 1.0;
+  std::vector<double> pI((size_t)P.N * P.KP * P.KP, 0.0);
+  for (int i = 0; i < P.N; ++i)
+    for (int j = 0; j < P.k; ++j) pI[((size_t)i * P.KP + j) * P.KP + j] = 1.0;
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return hipMemcpy(c->ws + off, src, n, hipMemcpyHostToDevice);
+  };
+  if (up(P.o_subj, P.subj.data(), sizeof(Subject) * P.N) != hipSuccess ||
+      up(P.o_slices, P.slices.data(), sizeof(Slice) * P.nslices) != hipSuccess ||
+      up(P.o_rs, P.range_slice.data(), sizeof(int32_t) * (P.nranges + 1)) != hipSuccess ||
+      up(P.o_srow0, srow0.data(), sizeof(int64_t) * P.N) != hipSuccess ||
+      up(P.o_sv, sv.data(), sizeof(int32_t) * P.N) != hipSuccess ||
+      up(P.o_xptr, X, sizeof(void*) * P.N) != hipSuccess ||
+      up(P.o_sc, &sc, sizeof sc) != hipSuccess ||
+      up(P.o_rho2, ones.data(), sizeof(double) * P.N) != hipSuccess ||
+      up(P.o_sigcur, eyeKP.data(), eyeKP.size() * 8) != hipSuccess ||
+      up(P.o_p64, pI.data(), pI.size() * 8) != hipSuccess)
+    return bail(fail(SRM_E_HIP, "upload of tables failed"));
+  s = upload_w0(c, W0);
+  if (s != SRM_OK) return bail(s);
+
+  const Ptrs q = ptrs(c);
+  ConvertArgs ca{c->at<const float* const>(P.o_xptr), c->at<int64_t>(P.o_srow0),
+                 c->at<int32_t>(P.o_sv), P.N, P.t, P.ldt, P.total_rows, q.xh, q.xl,
+                 c->at<double>(P.o_mu), c->at<double>(P.o_rowc), c->at<Scalars>(P.o_sc),
+                 P.prec};
+  if (launch_convert(c->stream, (int)((P.total_rows + 3) / 4), ca) != hipSuccess ||
+      launch_rowsum(c->stream, P.N, c->at<double>(P.o_rowc), c->at<Subject>(P.o_subj),
+                    c->at<double>(P.o_c)) != hipSuccess)
+    return bail(fail(SRM_E_HIP, "conversion launch failed"));
+  Scalars chk{};
+  if (hipMemcpyAsync(&chk, c->ws + P.o_sc, sizeof chk, hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(SRM_E_HIP, "conversion failed"));
+  if (chk.nonfinite) return bail(fail(SRM_E_NONFINITE, "X contains NaN or Inf"));
+
+  // First E-step with W_i = W0_i (P = I), rho^2 = 1, Sigma_s = I.
+  if (enqueue_estep(c, false) != hipSuccess)
+    return bail(fail(SRM_E_HIP, "first E-step launch failed"));
+  s = read_scalars(c, &chk);
+  if (s != SRM_OK) return bail(s);
+  *out = c;
+  return SRM_OK;
+}
+
+srm_status srm_em_step(srm_ctx* c, double* loglik) {
+  return srm_fit(c, 1, loglik);
+}
+
+srm_status srm_fit(srm_ctx* c, int32_t n_iter, double* loglik) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (n_iter < 0) return fail(SRM_E_ARG, "n_iter < 0");
+  const int first = c->iters;
+  srm_status s = run_iterations(c, n_iter);
+  if (s != SRM_OK) return s;
+  Scalars sc{};
+  s = read_scalars(c, &sc);
+  if (s != SRM_OK) return s;
+  if (loglik && n_iter > 0) {
+    // LL index j belongs to the parameters entering iteration j.
+    for (int it = 0; it < n_iter; ++it) {
+      const int idx = (first + it) & (kLLCapacity - 1);
+      HIP_OR_FAIL(hipMemcpy(loglik + it, c->ws + c->p.o_ll + sizeof(double) * idx,
+                            sizeof(double), hipMemcpyDeviceToHost));
+    }
+  }
+  return SRM_OK;
+}
+
+srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_new,
+                         float* S_out) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  const Plan& p = c->p;
+  if (i < 0 || i >= p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!X_new || !S_out) return fail(SRM_E_ARG, "NULL buffer");
+  if (t_new < 1) return fail(SRM_E_ARG, "t_new must be >= 1");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const Subject& su = p.subj[i];
+  const Ptrs q = ptrs(c);
+  // Scratch: the E-phase partial buffer (free between iterations), used in
+  // column chunks of [nsplit][KP][chunk] floats.
+  const int64_t cap = (int64_t)(p.zpart_bytes / ((size_t)p.KP * 4));
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(
+      std::min<int64_t>(64, (su.v + 2047) / 2048), cap / 64));
+  const int64_t chunk = std::max<int64_t>(64, std::min<int64_t>(
+      round_up(t_new, 64), cap / nsplit / 64 * 64));
+  if (chunk * nsplit > cap) return fail(SRM_E_WORKSPACE, "transform scratch too small");
+  const int rps = (int)((su.v + nsplit - 1) / nsplit);
+  for (int64_t c0 = 0; c0 < t_new; c0 += chunk) {
+    const int64_t tn = std::min(chunk, t_new - c0);
+    TArgs ta{q.ah, q.al, c->at<double>(p.o_mu), X_new + c0, c->at<float>(p.o_zpart),
+             su.row0, tn, t_new, su.v, rps, p.prec};
+    TFArgs tf{c->at<float>(p.o_zpart), c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP,
+              S_out + c0, tn, t_new, nsplit, p.k};
+    HIP_OR_FAIL(launch_transform(c->stream, p.KP, nsplit, ta, tf));
+  }
+  return SRM_OK;
+}
+
+srm_status srm_get_w(srm_ctx* c, int32_t i, float* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  const Plan& p = c->p;
+  if (i < 0 || i >= p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const Ptrs q = ptrs(c);
+  WArgs wa{q.ah, q.al, c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP, dst,
+           p.subj[i].row0, p.subj[i].v, p.k, p.prec};
+  HIP_OR_FAIL(launch_get_w(c->stream, p.KP, wa));
+  return SRM_OK;
+}
+
+srm_status srm_get_s(srm_ctx* c, float* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const Plan& p = c->p;
+  std::vector<double> s((size_t)p.KP * p.ldt);
+  HIP_OR_FAIL(hipMemcpyAsync(s.data(), c->ws + p.o_s64cur, s.size() * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  std::vector<float> f((size_t)p.k * p.t);
+  for (int j = 0; j < p.k; ++j)
+    for (int64_t col = 0; col < p.t; ++col)
+      f[(size_t)j * p.t + col] = (float)s[(size_t)j * p.ldt + col];
+  HIP_OR_FAIL(hipMemcpyAsync(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  return SRM_OK;
+}
+
+srm_status srm_get_rho2(srm_ctx* c, double* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_rho2, sizeof(double) * c->p.N,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  return SRM_OK;
+}
+
+srm_status srm_get_sigma_s(srm_ctx* c, double* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const Plan& p = c->p;
+  std::vector<double> s((size_t)p.KP * p.KP);
+  HIP_OR_FAIL(hipMemcpyAsync(s.data(), c->ws + p.o_sigcur, s.size() * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  for (int a = 0; a < p.k; ++a)
+    for (int b = 0; b < p.k; ++b) dst[(size_t)a * p.k + b] = s[(size_t)a * p.KP + b];
+  return SRM_OK;
+}
+
+srm_status srm_get_mu(srm_ctx* c, int32_t i, double* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (i < 0 || i >= c->p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_mu + sizeof(double) * c->p.subj[i].row0,
+                             sizeof(double) * c->p.subj[i].v, hipMemcpyDeviceToDevice,
+                             c->stream));
+  return SRM_OK;
+}
+
+srm_status srm_get_loglik(srm_ctx* c, double* dst, int32_t capacity, int32_t* count) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!count) return fail(SRM_E_ARG, "count is NULL");
+  Scalars sc{};
+  HIP_OR_FAIL(hipMemcpyAsync(&sc, c->ws + c->p.o_sc, sizeof sc, hipMemcpyDeviceToHost,
+                             c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  *count = sc.ll_count;
+  if (dst) {
+    const int n = std::min(std::min(capacity, sc.ll_count), kLLCapacity);
+    for (int j = 0; j < n; ++j)
+      HIP_OR_FAIL(hipMemcpy(dst + j, c->ws + c->p.o_ll + sizeof(double) * j, sizeof(double),
+                            hipMemcpyDeviceToHost));
+  }
+  return SRM_OK;
+}
+
+srm_status srm_iterations(const srm_ctx* c, int32_t* n) {
+  if (!c || !n) return fail(SRM_E_ARG, "NULL argument");
+  *n = c->iters;
+  return SRM_OK;
+}
+
+const char* srm_last_error(void) { return g_err.c_str(); }
+
+void srm_free(srm_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Internal layout shared by the host planner (srm_api.cpp) and the kernels
+// (srm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srm {
+
+// Rows of every subject are padded to a multiple of 32 (one MFMA K-block in
+// the E-phase); TRs to a multiple of 64 (one MFMA K-step pair in the M-phase,
+// one wave's column panel in the E-phase).  Padding is zero.
+constexpr int kRowPad = 32;
+constexpr int kColPad = 64;
+constexpr int kMaxK = 128;
+
+// One contiguous run of rows of a single subject handled by one E-phase
+// workgroup (a workgroup's equal row range split at subject boundaries).
+struct Slice {
+  int64_t row0;   // first global (padded) row
+  int32_t nrows;  // multiple of 32
+  int32_t subj;
+};
+
+struct Subject {
+  int64_t row0;     // first global row of the subject
+  int32_t v;        // true voxel count
+  int32_t vp;       // padded row count
+  int32_t s_beg;    // its slices [s_beg, s_end)
+  int32_t s_end;
+};
+
+// Device-resident scalars of the current EM state.
+struct Scalars {
+  double rho0;          // sum_i rho_i^-2 (Eq. 8)
+  double logdet;        // log|I + rho0 Sigma_s|
+  double sum_vlogrho;   // sum_i v_i log rho_i^2
+  double sum_c_rho;     // sum_i c_i / rho_i^2
+  double tau_cur;       // tr(Sigma_s) of the current state
+  double tau_new;       // tr(Sigma_s) produced by the latest E-step
+  int32_t ll_count;     // log-likelihoods written so far
+  int32_t status;       // 0 ok, else an srm_status code raised on the device
+  int32_t nonfinite;    // set by the conversion kernel
+  int32_t pad_;
+};
+
+constexpr int kLLCapacity = 1 << 16;
+
+// Precision codes (match srm_prec).
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_BF16X2 = 2 };
+
+// Kernel argument blocks (passed by value; filled by the host planner).
+struct ConvertArgs {
+  const float* const* X;     // device array of N device pointers
+  const int64_t* subj_row0;  // [N] first global row of each subject
+  const int32_t* subj_v;     // [N]
+  int32_t N;
+  int64_t t, ldt, total_rows;
+  void* xh;
+  void* xl;
+  double* mu;
+  double* rowc;
+  Scalars* sc;
+  int32_t prec;
+};
+
+struct MArgs {
+  const void* xh;
+  const void* xl;
+  const void* sh;  // S records (hi or FP32)
+  const void* sl;  // S records (lo)
+  void* ah;        // A records out (hi or FP32)
+  void* al;        // A records out (lo)
+  int64_t ldt;
+  int64_t total_rows;
+  int64_t ntiles;  // ceil(total_rows / 64)
+  int64_t tiles_per_wg;
+};
+
+struct EArgs {
+  const void* xh;
+  const void* xl;
+  const void* ah;
+  const void* al;
+  const Slice* slices;
+  const int32_t* range_slice;  // [nranges + 1]
+  float* zpart;                // [nslices][KP][ldt]
+  float* gpart;                // [nslices][KP][KP]
+  int64_t ldt;
+  int32_t npanel;
+  int32_t want_gram;
+};
+
+struct RArgs {
+  const float* zpart;
+  const Subject* subj;
+  const double* P64;  // [N][KP][KP]
+  const double* rho2;
+  double* ygrp;       // [ngrp][KP][ldt]
+  int32_t N;
+  int32_t gsub;
+  int64_t ldt;
+};
+
+struct PrepArgs {
+  const double* rho2;
+  const double* c;
+  const Subject* subj;
+  const double* sig;  // [KP][KP] current Sigma_s
+  double* M;          // [KP][KP] out (zero padded)
+  double* work;       // global scratch [2][KP][KP+1] (used when KP > 96)
+  Scalars* sc;
+  int32_t N;
+  int32_t k;
+};
+
+struct SArgs {
+  const double* ygrp;
+  const double* M;
+  double* s64;     // [KP][ldt]
+  void* sh;        // S records (hi or FP32)
+  void* sl;        // S records (lo)
+  double* sspart;  // [nblk][KP][KP]
+  double* trpart;  // [nblk]
+  int32_t ngrp;
+  int32_t k;
+  int64_t t, ldt;
+};
+
+struct FinArgs {
+  const double* sspart;
+  const double* trpart;
+  const double* M;
+  double* sig_new;
+  double* ll;
+  Scalars* sc;
+  int32_t nblk;
+  int32_t k;
+  int64_t t;
+  double Vtot;
+};
+
+struct CopyArgs {
+  const double* s64_new;
+  double* s64_cur;
+  const uint4* srec_new;
+  uint4* srec_cur;
+  const double* sig_new;
+  double* sig_cur;
+  Scalars* sc;
+  int64_t n_s64;
+  int64_t n_srec16;  // in uint4 units
+  int32_t n_sig;
+};
+
+struct QArgs {
+  const float* gpart;
+  const Subject* subj;
+  const double* c;
+  double* rho2;
+  double* P64;
+  double* work;  // [N][2][KP][KP+1] global scratch (KP > 96)
+  Scalars* sc;
+  int32_t k;
+  int64_t t;
+};
+
+struct WArgs {
+  const void* ah;
+  const void* al;
+  const double* P;  // [KP][KP] of subject i
+  float* dst;       // v x k
+  int64_t row0;
+  int32_t v;
+  int32_t k;
+  int32_t prec;
+};
+
+struct TArgs {
+  const void* ah;
+  const void* al;
+  const double* mu;
+  const float* X;   // v rows, row stride ldx; columns [0, tn) used
+  float* part;      // [nsplit][KP][tn]
+  int64_t row0;
+  int64_t tn;
+  int64_t ldx;
+  int32_t v;
+  int32_t rows_per_split;
+  int32_t prec;
+};
+
+struct TFArgs {
+  const float* part;
+  const double* P;
+  float* out;  // k rows, row stride ldo; columns [0, tn)
+  int64_t tn;
+  int64_t ldo;
+  int32_t nsplit;
+  int32_t k;
+};
+
+}  // namespace srm

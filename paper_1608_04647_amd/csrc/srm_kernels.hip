@@ -1,0 +1,1059 @@
+// HIP kernels (gfx950 / CDNA4) of the SRM EM sweep, arXiv 1608.04647 Sec. II.
+//
+// Data layout in HBM (all row-major, zero padded):
+//   Xhat   : sum_i vp_i rows x ldt columns, one plane (FP32 or BF16) or two
+//            planes (BF16 hi, BF16 lo).  vp_i = round_up(v_i, 32),
+//            ldt = round_up(t, 64).  Subjects are stacked; row r is global.
+//   A, S   : "records", i.e. the exact per-lane operand layout of the
+//            matrix-core instructions, so a wave loads an operand tile with one
+//            contiguous 1-2 KiB access and never shuffles it.
+//     A record (32 rows x 16 columns of A = Xhat S^T, or of W0 at start):
+//            lane l holds A[32 rb + row(l/16, e)][16 jb + l%16], e = 0..7,
+//            row(g, e) = 4 g + (e & 3) + 16 (e >> 2).  This is at once the
+//            16x16 accumulator layout of two stacked M-phase output tiles and
+//            the K = rows operand layout of the E-phase.
+//     S record, BF16 forms (32 TRs x 16 features):
+//            lane l holds S[16 jb + l%16][32 tb + 8 (l/16) + e], e = 0..7.
+//     S record, FP32 (16 TRs x 16 features):
+//            lane l holds S[16 jb + l%16][16 tb + 4 (l/16) + s], s = 0..3.
+//
+// Per EM iteration (deferred W: W_i = A_i P_i with P_i = (A_i^T A_i)^-1/2):
+//   k_mphase   A = Xhat S^T                       (Eq. 4 numerator, A_i)
+//   k_ephase   Z_s = A_s^T Xhat_s, G_s = A_s^T A_s per slice (Eq. 10 partials,
+//              Eq. 4 Gram), one streaming pass over Xhat and A
+//   k_polar    G_i -> Jacobi eig (FP64) -> P_i, tr(W_i^T A_i), rho_i^2
+//   k_ereduce  Y = sum_i rho_i^-2 P_i sum_s Z_s   (Eq. 10 reduction, FP64)
+//   k_post_prep rho0, M = (Sigma_s^-1 + rho0 I)^-1, log-det (Eq. 7-8, FP64)
+//   k_post_s   S = M Y (Eq. 10 with Sigma_s [I - rho0 M] = M), S S^T partials
+//   k_post_fin Sigma_s = M + S S^T / t (Eq. 11), tr(Sigma_s), log-likelihood
+// All reductions run in a fixed order: results are bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "srm_internal.h"
+
+namespace srm {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma_bf16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b),
+                                                 c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (inputs are finite).
+__device__ __forceinline__ uint32_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t h) {
+  return __uint_as_float(h << 16);
+}
+
+// hi = bf16(v), lo = bf16(v - hi), packed 8 -> uint4 each.
+__device__ __forceinline__ void split8(const float (&v)[8], uint4& hi,
+                                       uint4& lo) {
+  uint32_t h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    h[e] = f2bf(v[e]);
+    l[e] = f2bf(v[e] - bf2f(h[e]));
+  }
+  hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                  h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+  lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16),
+                  l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+}
+
+// Workgroup ids are dealt round-robin to the 8 XCDs; map them so that
+// consecutive logical ids share an XCD (and its L2).
+__device__ __forceinline__ int xcd_remap(int h, int G) {
+  const int q = G >> 3, r = G & 7;
+  const int x = h & 7, l = h >> 3;
+  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order block sum over 256 threads (result valid in every thread).
+__device__ double block_sum256(double v, double* red /* >= 4 */) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: demean (Algorithm 1), convert, per-row ||xhat||^2.
+// One wave per (padded) global row.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= a.total_rows) return;
+  int lo = 0, hi = a.N - 1;  // last subject with row0 <= r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.subj_row0[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  const int64_t lr = r - a.subj_row0[lo];
+  const bool real = lr < a.subj_v[lo];
+  const float* src = real ? a.X[lo] + lr * a.t : nullptr;
+  double s = 0.0;
+  bool bad = false;
+  if (real) {
+    for (int64_t c = lane; c < a.t; c += 64) {
+      const float x = src[c];
+      bad |= !isfinite(x);
+      s += (double)x;
+    }
+  }
+  s = wave_sum(s);
+  const double mu = real ? s / (double)a.t : 0.0;
+  double sq = 0.0;
+  for (int64_t c = lane; c < a.ldt; c += 64) {
+    const float f = (real && c < a.t) ? (float)((double)src[c] - mu) : 0.0f;
+    const int64_t o = r * a.ldt + c;
+    if (a.prec == P_FP32) {
+      ((float*)a.xh)[o] = f;
+      sq += (double)f * (double)f;
+    } else {
+      const uint32_t h = f2bf(f);
+      ((uint16_t*)a.xh)[o] = (uint16_t)h;
+      double st = (double)bf2f(h);
+      if (a.prec == P_BF16X2) {
+        const uint32_t l = f2bf(f - bf2f(h));
+        ((uint16_t*)a.xl)[o] = (uint16_t)l;
+        st += (double)bf2f(l);
+      }
+      sq += st * st;
+    }
+  }
+  sq = wave_sum(sq);
+  if (lane == 0) {
+    a.mu[r] = mu;
+    a.rowc[r] = sq;
+  }
+  if (bad) a.sc->nonfinite = 1;
+}
+
+// c_i = ||Xhat_i||_F^2 from the per-row sums (fixed order).
+__global__ __launch_bounds__(256) void k_rowsum(const double* rowc,
+                                                const Subject* subj,
+                                                double* c) {
+  __shared__ double red[4];
+  const Subject s = subj[blockIdx.x];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < s.vp; r += 256) acc += rowc[s.row0 + r];
+  acc = block_sum256(acc, red);
+  if (threadIdx.x == 0) c[blockIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// M-phase: A = Xhat S^T over all subjects' rows (one grouped launch).
+// Workgroup = 4 waves; each wave owns 64-row tiles (4 MFMA row blocks) and the
+// full K (= features, padded) width; TRs are the contraction.
+// ---------------------------------------------------------------------------
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void k_mphase(MArgs a) {
+  constexpr int NB = KP / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t tb0 = (int64_t)blockIdx.x * a.tiles_per_wg;
+  int64_t te = tb0 + a.tiles_per_wg;
+  if (te > a.ntiles) te = a.ntiles;
+  for (int64_t tile = tb0 + wave; tile < te; tile += 4) {
+    const int64_t rowt = tile * 64;
+    const bool h1 = rowt + 32 < a.total_rows;  // second 32-row half valid
+    f32x4 acc[4][NB];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) acc[mb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if constexpr (PREC == P_FP32) {
+      const float* X = (const float*)a.xh;
+      const float4* SR = (const float4*)a.sh;
+      const int64_t nstep = a.ldt / 16;
+      for (int64_t tb = 0; tb < nstep; ++tb) {
+        float4 x4[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          if (mb < 2 || h1)
+            x4[mb] = *(const float4*)(X + (rowt + 16 * mb + n) * a.ldt +
+                                      16 * tb + 4 * g);
+          else
+            x4[mb] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        float4 s4[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) s4[jb] = SR[(tb * NB + jb) * 64 + lane];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          if (mb >= 2 && !h1) continue;
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb) {
+            acc[mb][jb] = mfma_f32(x4[mb].x, s4[jb].x, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[mb].y, s4[jb].y, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[mb].z, s4[jb].z, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[mb].w, s4[jb].w, acc[mb][jb]);
+          }
+        }
+      }
+    } else {
+      const uint16_t* XH = (const uint16_t*)a.xh;
+      const uint16_t* XL = (const uint16_t*)a.xl;
+      const uint4* SH = (const uint4*)a.sh;
+      const uint4* SL = (const uint4*)a.sl;
+      const int64_t nstep = a.ldt / 32;
+      for (int64_t tb = 0; tb < nstep; ++tb) {
+        uint4 xh4[4], xl4[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const int64_t o = (rowt + 16 * mb + n) * a.ldt + 32 * tb + 8 * g;
+          if (mb < 2 || h1) {
+            xh4[mb] = *(const uint4*)(XH + o);
+            if constexpr (PREC == P_BF16X2) xl4[mb] = *(const uint4*)(XL + o);
+          } else {
+            xh4[mb] = make_uint4(0, 0, 0, 0);
+            xl4[mb] = make_uint4(0, 0, 0, 0);
+          }
+        }
+        uint4 sh4[NB], sl4[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          sh4[jb] = SH[(tb * NB + jb) * 64 + lane];
+          sl4[jb] = SL[(tb * NB + jb) * 64 + lane];
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          if (mb >= 2 && !h1) continue;
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb) {
+            acc[mb][jb] = mfma_bf16(xh4[mb], sh4[jb], acc[mb][jb]);
+            acc[mb][jb] = mfma_bf16(xh4[mb], sl4[jb], acc[mb][jb]);
+            if constexpr (PREC == P_BF16X2)
+              acc[mb][jb] = mfma_bf16(xl4[mb], sh4[jb], acc[mb][jb]);
+          }
+        }
+      }
+    }
+    // Accumulator lane l holds A[rowt + 16 mb + 4 g + i][16 jb + n]; two
+    // stacked row blocks are exactly one A record.
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !h1) break;
+      const int64_t rb = rowt / 32 + h;
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = acc[2 * h + (e >> 2)][jb][e & 3];
+        const int64_t rec = (rb * NB + jb) * 64 + lane;
+        if constexpr (PREC == P_FP32) {
+          float4* AR = (float4*)a.ah;
+          AR[rec * 2] = make_float4(v[0], v[1], v[2], v[3]);
+          AR[rec * 2 + 1] = make_float4(v[4], v[5], v[6], v[7]);
+        } else {
+          uint4 hi, lo;
+          split8(v, hi, lo);
+          ((uint4*)a.ah)[rec] = hi;
+          ((uint4*)a.al)[rec] = lo;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// E-phase: per slice s (rows of one subject), Z_s = A_s^T Xhat_s (KP x ldt)
+// and, for the M-step, G_s = A_s^T A_s (upper 16x16 tiles).  Workgroup =
+// 4 waves, each wave a 64-TR column panel; rows are the contraction.
+// Workgroup w owns an equal share of all rows (split at subject boundaries
+// into slices); the npanel column panels of a row range sit on one XCD.
+// ---------------------------------------------------------------------------
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void k_ephase(EArgs a) {
+  constexpr int NB = KP / 16;
+  constexpr int NPAIR = NB * (NB + 1) / 2;
+  constexpr int NG = (NPAIR + 3) / 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int range = w / a.npanel, panel = w % a.npanel;
+  const int64_t cbase = (int64_t)panel * 256 + wave * 64;
+  const bool do_z = cbase < a.ldt;
+  const bool do_g = a.want_gram && panel == 0;
+  if (!do_z && !do_g) return;
+  const int sb = a.range_slice[range], se = a.range_slice[range + 1];
+
+  for (int s = sb; s < se; ++s) {
+    const Slice sl = a.slices[s];
+    f32x4 acc[NB][4];
+    f32x4 gacc[NG];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[jb][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int nblk = sl.nrows / 32;
+    for (int blk = 0; blk < nblk; ++blk) {
+      const int64_t row0 = sl.row0 + 32 * blk;
+      const int64_t rb = row0 / 32;
+      if constexpr (PREC == P_FP32) {
+        const float4* AR = (const float4*)a.ah;
+        float av[NB][8];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          const int64_t rec = (rb * NB + jb) * 64 + lane;
+          const float4 p0 = AR[rec * 2], p1 = AR[rec * 2 + 1];
+          av[jb][0] = p0.x; av[jb][1] = p0.y; av[jb][2] = p0.z; av[jb][3] = p0.w;
+          av[jb][4] = p1.x; av[jb][5] = p1.y; av[jb][6] = p1.z; av[jb][7] = p1.w;
+        }
+        if (do_z) {
+          const float* X = (const float*)a.xh;
+          float4 xv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int64_t r = row0 + 4 * g + (e & 3) + 16 * (e >> 2);
+            xv[e] = *(const float4*)(X + r * a.ldt + cbase + 4 * n);
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+              acc[jb][0] = mfma_f32(av[jb][e], xv[e].x, acc[jb][0]);
+              acc[jb][1] = mfma_f32(av[jb][e], xv[e].y, acc[jb][1]);
+              acc[jb][2] = mfma_f32(av[jb][e], xv[e].z, acc[jb][2]);
+              acc[jb][3] = mfma_f32(av[jb][e], xv[e].w, acc[jb][3]);
+            }
+        }
+        if (do_g) {
+          int p = 0;
+#pragma unroll
+          for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+            for (int j2 = j1; j2 < NB; ++j2, ++p)
+              if ((p & 3) == wave)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                  gacc[p >> 2] = mfma_f32(av[j1][e], av[j2][e], gacc[p >> 2]);
+        }
+      } else {
+        const uint4* AH = (const uint4*)a.ah;
+        const uint4* AL = (const uint4*)a.al;
+        uint4 ah[NB], al[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          const int64_t rec = (rb * NB + jb) * 64 + lane;
+          ah[jb] = AH[rec];
+          al[jb] = AL[rec];
+        }
+        if (do_z) {
+          const uint16_t* XH = (const uint16_t*)a.xh;
+          const uint16_t* XL = (const uint16_t*)a.xl;
+          uint2 xv[8], xw[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int64_t r = row0 + 4 * g + (e & 3) + 16 * (e >> 2);
+            const int64_t o = r * a.ldt + cbase + 4 * n;
+            xv[e] = *(const uint2*)(XH + o);
+            if constexpr (PREC == P_BF16X2) xw[e] = *(const uint2*)(XL + o);
+          }
+          // In-register 8x4 transpose: operand q holds column 4n+q of the
+          // 8 rows, two rows per dword.
+          uint4 bh[4], bl[4];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint2 u0 = xv[2 * d], u1 = xv[2 * d + 1];
+            const uint32_t c0 = (u0.x & 0xffffu) | (u1.x << 16);
+            const uint32_t c1 = (u0.x >> 16) | (u1.x & 0xffff0000u);
+            const uint32_t c2 = (u0.y & 0xffffu) | (u1.y << 16);
+            const uint32_t c3 = (u0.y >> 16) | (u1.y & 0xffff0000u);
+            ((uint32_t*)&bh[0])[d] = c0;
+            ((uint32_t*)&bh[1])[d] = c1;
+            ((uint32_t*)&bh[2])[d] = c2;
+            ((uint32_t*)&bh[3])[d] = c3;
+            if constexpr (PREC == P_BF16X2) {
+              const uint2 w0 = xw[2 * d], w1 = xw[2 * d + 1];
+              ((uint32_t*)&bl[0])[d] = (w0.x & 0xffffu) | (w1.x << 16);
+              ((uint32_t*)&bl[1])[d] = (w0.x >> 16) | (w1.x & 0xffff0000u);
+              ((uint32_t*)&bl[2])[d] = (w0.y & 0xffffu) | (w1.y << 16);
+              ((uint32_t*)&bl[3])[d] = (w0.y >> 16) | (w1.y & 0xffff0000u);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+              acc[jb][q] = mfma_bf16(ah[jb], bh[q], acc[jb][q]);
+              acc[jb][q] = mfma_bf16(al[jb], bh[q], acc[jb][q]);
+              if constexpr (PREC == P_BF16X2)
+                acc[jb][q] = mfma_bf16(ah[jb], bl[q], acc[jb][q]);
+            }
+        }
+        if (do_g) {
+          int p = 0;
+#pragma unroll
+          for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+            for (int j2 = j1; j2 < NB; ++j2, ++p)
+              if ((p & 3) == wave) {
+                gacc[p >> 2] = mfma_bf16(ah[j1], ah[j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(ah[j1], al[j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(al[j1], ah[j2], gacc[p >> 2]);
+              }
+        }
+      }
+    }
+    // Z tile: lane holds Z[16 jb + 4 g + i][cbase + 4 n + q].
+    if (do_z) {
+      float* zp = a.zpart + (int64_t)s * KP * a.ldt;
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 16 * jb + 4 * g + i;
+          *(float4*)(zp + j * a.ldt + cbase + 4 * n) =
+              make_float4(acc[jb][0][i], acc[jb][1][i], acc[jb][2][i],
+                          acc[jb][3][i]);
+        }
+    }
+    if (do_g) {
+      float* gp = a.gpart + (int64_t)s * KP * KP;
+      int p = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NB; ++j2, ++p)
+          if ((p & 3) == wave)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p >> 2][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y = sum_i rho_i^-2 P_i (sum_{s in i} Z_s)   (Eq. 10), FP64.
+// Grid: (column tiles of CT TRs) x (groups of gsub subjects).
+// ---------------------------------------------------------------------------
+
+template <int KP, int CT>
+__global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
+  constexpr int TPC = 256 / CT;
+  constexpr int NJ = KP / TPC;
+  __shared__ double Zs[KP][CT];
+  __shared__ double Ps[KP][KP + 1];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  const int c = tid % CT, jr = tid / CT;
+  double out[NJ > 0 ? NJ : 1];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) out[u] = 0.0;
+  const int i0 = blockIdx.y * a.gsub;
+  int i1 = i0 + a.gsub;
+  if (i1 > a.N) i1 = a.N;
+  for (int i = i0; i < i1; ++i) {
+    const Subject su = a.subj[i];
+    for (int idx = tid; idx < KP * CT; idx += 256) {
+      const int j = idx / CT, cc = idx % CT;
+      double s = 0.0;
+      for (int sl = su.s_beg; sl < su.s_end; ++sl)
+        s += (double)a.zpart[((int64_t)sl * KP + j) * a.ldt + c0 + cc];
+      Zs[j][cc] = s;
+    }
+    const double* P = a.P64 + (int64_t)i * KP * KP;
+    for (int idx = tid; idx < KP * KP; idx += 256) Ps[idx / KP][idx % KP] = P[idx];
+    __syncthreads();
+    const double w = 1.0 / a.rho2[i];
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = jr + TPC * u;
+      double s = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < KP; ++b) s += Ps[j][b] * Zs[b][c];
+      out[u] += w * s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = jr + TPC * u;
+    a.ygrp[((int64_t)blockIdx.y * KP + j) * a.ldt + c0 + c] = out[u];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense FP64 helpers for k x k matrices (one workgroup of 256 threads).
+// Storage row-major with leading dimension ld; pointers may be LDS or global.
+// ---------------------------------------------------------------------------
+// In-place lower Cholesky (right-looking).  Returns false if not PD.
+__device__ bool chol_lower(double* A, int k, int ld, int* flag) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double d = A[j * ld + j];
+      if (!(d > 0.0)) {
+        *flag = 1;
+        A[j * ld + j] = 1.0;
+      } else {
+        A[j * ld + j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double djj = A[j * ld + j];
+    for (int i = j + 1 + tid; i < k; i += 256) A[i * ld + j] /= djj;
+    __syncthreads();
+    const int m = k - 1 - j;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int r = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= r) A[r * ld + c] -= A[r * ld + j] * A[c * ld + j];
+    }
+    __syncthreads();
+  }
+  const bool ok = *flag == 0;
+  __syncthreads();
+  return ok;
+}
+
+// X = L^-1 for lower-triangular L (column-parallel forward substitution).
+__device__ void tri_inv_lower(const double* L, double* X, int k, int ld) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int r = idx / k, c = idx % k;
+    if (r < c) X[r * ld + c] = 0.0;
+  }
+  for (int c = tid; c < k; c += 256) {
+    X[c * ld + c] = 1.0 / L[c * ld + c];
+    for (int r = c + 1; r < k; ++r) {
+      double s = 0.0;
+      for (int m = c; m < r; ++m) s += L[r * ld + m] * X[m * ld + c];
+      X[r * ld + c] = -s / L[r * ld + r];
+    }
+  }
+  __syncthreads();
+}
+
+// out = X^T X for lower-triangular X (full symmetric result, row-major ldo).
+__device__ void ltl(const double* X, int k, int ld, double* out, int ldo) {
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    const int a = idx / k, b = idx % k;
+    const int m0 = a > b ? a : b;
+    double s = 0.0;
+    for (int m = m0; m < k; ++m) s += X[m * ld + a] * X[m * ld + b];
+    out[a * ldo + b] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Posterior preparation (one workgroup): rho0 (Eq. 8), Cholesky of Sigma_s,
+// Sigma_s^-1, M = (Sigma_s^-1 + rho0 I)^-1 (Eq. 7), log|I + rho0 Sigma_s| and
+// the likelihood's data terms.
+// ---------------------------------------------------------------------------
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_post_prep(PrepArgs a) {
+  constexpr int LD = KP + 1;
+  constexpr bool IN_LDS = KP <= 96;
+  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
+  __shared__ double red[4];
+  __shared__ int flag;
+  double* A = IN_LDS ? lds : a.work;
+  double* B = IN_LDS ? lds + KP * LD : a.work + KP * LD;
+  const int tid = threadIdx.x, k = a.k;
+
+  double r0 = 0.0, vl = 0.0, cr = 0.0;
+  for (int i = tid; i < a.N; i += 256) {
+    const double r = a.rho2[i];
+    r0 += 1.0 / r;
+    vl += (double)a.subj[i].v * log(r);
+    cr += a.c[i] / r;
+  }
+  const double rho0 = block_sum256(r0, red);
+  const double svl = block_sum256(vl, red);
+  const double scr = block_sum256(cr, red);
+
+  for (int idx = tid; idx < k * k; idx += 256)
+    A[(idx / k) * LD + idx % k] = a.sig[(idx / k) * KP + idx % k];
+  __syncthreads();
+  bool ok = chol_lower(A, k, LD, &flag);
+  double ld1 = 0.0;
+  for (int j = tid; j < k; j += 256) ld1 += 2.0 * log(A[j * LD + j]);
+  ld1 = block_sum256(ld1, red);
+  tri_inv_lower(A, B, k, LD);
+  ltl(B, k, LD, A, LD);  // A = Sigma_s^-1
+  for (int j = tid; j < k; j += 256) A[j * LD + j] += rho0;
+  __syncthreads();
+  ok = chol_lower(A, k, LD, &flag) && ok;
+  double ld2 = 0.0;
+  for (int j = tid; j < k; j += 256) ld2 += 2.0 * log(A[j * LD + j]);
+  ld2 = block_sum256(ld2, red);
+  tri_inv_lower(A, B, k, LD);
+  for (int idx = tid; idx < KP * KP; idx += 256) a.M[idx] = 0.0;
+  __syncthreads();
+  ltl(B, k, LD, a.M, KP);
+  if (tid == 0) {
+    a.sc->rho0 = rho0;
+    a.sc->sum_vlogrho = svl;
+    a.sc->sum_c_rho = scr;
+    a.sc->logdet = ld1 + ld2;  // log|Sigma_s| + log|Sigma_s^-1 + rho0 I|
+    if (!ok && a.sc->status == 0) a.sc->status = 5;  // SRM_E_NOTPD
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S = M Y on column tiles (Eq. 10), its records, S S^T and tr(Y^T S) partials.
+// ---------------------------------------------------------------------------
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void k_post_s(SArgs a) {
+  constexpr int CT = 16;
+  constexpr int NB = KP / 16;
+  __shared__ double Ys[KP][CT];
+  __shared__ double Ss[KP][CT];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  for (int idx = tid; idx < KP * CT; idx += 256) {
+    const int j = idx / CT, cc = idx % CT;
+    double s = 0.0;
+    for (int gq = 0; gq < a.ngrp; ++gq)
+      s += a.ygrp[((int64_t)gq * KP + j) * a.ldt + c0 + cc];
+    Ys[j][cc] = s;
+  }
+  __syncthreads();
+  double tr = 0.0;
+  for (int idx = tid; idx < KP * CT; idx += 256) {
+    const int j = idx / CT, cc = idx % CT;
+    const int64_t col = c0 + cc;
+    double s = 0.0;
+    if (j < a.k && col < a.t) {
+      for (int b = 0; b < a.k; ++b) s += a.M[j * KP + b] * Ys[b][cc];
+    }
+    Ss[j][cc] = s;
+    tr += s * Ys[j][cc];
+    a.s64[(int64_t)j * a.ldt + col] = s;
+    const int jb = j >> 4;
+    if constexpr (PREC == P_FP32) {
+      const int64_t tb = col >> 4;
+      const int lane = (j & 15) + 16 * (int)((col & 15) >> 2);
+      ((float*)a.sh)[((tb * NB + jb) * 64 + lane) * 4 + (col & 3)] = (float)s;
+    } else {
+      const int64_t tb = col >> 5;
+      const int lane = (j & 15) + 16 * (int)((col & 31) >> 3);
+      const int64_t o = ((tb * NB + jb) * 64 + lane) * 8 + (col & 7);
+      const float f = (float)s;
+      const uint32_t h = f2bf(f);
+      ((uint16_t*)a.sh)[o] = (uint16_t)h;
+      ((uint16_t*)a.sl)[o] = (uint16_t)f2bf(f - bf2f(h));
+    }
+  }
+  tr = block_sum256(tr, red);
+  if (tid == 0) a.trpart[blockIdx.x] = tr;
+  for (int idx = tid; idx < KP * KP; idx += 256) {
+    const int p = idx / KP, q = idx % KP;
+    double s = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) s += Ss[p][cc] * Ss[q][cc];
+    a.sspart[(int64_t)blockIdx.x * KP * KP + idx] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sigma_s = M + S S^T / t (Eq. 11), tau = tr(Sigma_s), log-likelihood.
+// ---------------------------------------------------------------------------
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_post_fin(FinArgs a) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double tau = 0.0;
+  for (int idx = tid; idx < KP * KP; idx += 256) {
+    const int p = idx / KP, q = idx % KP;
+    double v = 0.0;
+    if (p < a.k && q < a.k) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int b = 0; b < a.nblk; ++b) {
+        s1 += a.sspart[(int64_t)b * KP * KP + p * KP + q];
+        s2 += a.sspart[(int64_t)b * KP * KP + q * KP + p];
+      }
+      const double v1 = a.M[p * KP + q] + s1 / (double)a.t;
+      const double v2 = a.M[q * KP + p] + s2 / (double)a.t;
+      v = 0.5 * (v1 + v2);
+    }
+    a.sig_new[idx] = v;
+    if (p == q) tau += v;
+  }
+  tau = block_sum256(tau, red);
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int b = 0; b < a.nblk; ++b) tr += a.trpart[b];
+    const Scalars* s = a.sc;
+    const double t = (double)a.t;
+    const double ll = -0.5 * (t * a.Vtot * 1.8378770664093454836 +
+                              t * s->sum_vlogrho + t * s->logdet +
+                              s->sum_c_rho - tr);
+    const int n = a.sc->ll_count;
+    a.ll[n & (kLLCapacity - 1)] = ll;
+    a.sc->ll_count = n + 1;
+    a.sc->tau_new = tau;
+  }
+}
+
+// Start of an iteration: the previous E-step's S, Sigma_s, tau become current.
+
+__global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = i0; i < a.n_s64; i += stride) a.s64_cur[i] = a.s64_new[i];
+  for (int64_t i = i0; i < a.n_srec16; i += stride) a.srec_cur[i] = a.srec_new[i];
+  for (int64_t i = i0; i < a.n_sig; i += stride) a.sig_cur[i] = a.sig_new[i];
+  if (i0 == 0) a.sc->tau_cur = a.sc->tau_new;
+}
+
+// ---------------------------------------------------------------------------
+// Polar factor and rho update, one workgroup per subject (Eq. 4, reading of
+// Eq. 5): G_i = sum_s G_s (FP64), cyclic Jacobi G_i = V diag(lambda) V^T,
+// P_i = V diag(lambda^-1/2) V^T, tr(W_i^T A_i) = sum_j sqrt(lambda_j),
+// rho_i^2 = (c_i - 2 tr(W_i^T A_i) + t tau) / (t v_i).
+// ---------------------------------------------------------------------------
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_polar(QArgs a) {
+  constexpr int LD = KP + 1;
+  constexpr bool IN_LDS = KP <= 96;
+  constexpr int MAXP = (KP + 1) / 2;
+  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
+  __shared__ double cs_[MAXP], sn_[MAXP];
+  __shared__ int pp_[MAXP], qq_[MAXP];
+  __shared__ int rotated;
+  __shared__ double red[4];
+  const int i = blockIdx.x, tid = threadIdx.x, k = a.k;
+  double* G = IN_LDS ? lds : a.work + (int64_t)i * 2 * KP * LD;
+  double* V = G + KP * LD;
+  const Subject su = a.subj[i];
+
+  // G_i from the slices' upper 16x16 tiles, mirrored.
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int p = idx / k, q = idx % k;
+    const int r = p <= q ? p : q, cc = p <= q ? q : p;
+    double s = 0.0;
+    for (int sl = su.s_beg; sl < su.s_end; ++sl)
+      s += (double)a.gpart[(int64_t)sl * KP * KP + r * KP + cc];
+    G[p * LD + q] = s;
+    V[p * LD + q] = (p == q) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // Cyclic Jacobi, round-robin (circle) ordering of the k(k-1)/2 pairs.
+  const int m = (k + 1) & ~1;  // even player count (index k is a dummy)
+  const int npair = m / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < m - 1; ++rnd) {
+      if (tid < npair) {
+        int p, q;
+        if (tid == 0) {
+          p = m - 1;
+          q = rnd;
+        } else {
+          p = (rnd + tid) % (m - 1);
+          q = (rnd - tid + m - 1) % (m - 1);
+        }
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          const double app = G[p * LD + p], aqq = G[q * LD + q];
+          const double apq = G[p * LD + q];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) /
+                              (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            rotated = 1;
+          }
+        }
+        cs_[tid] = c;
+        sn_[tid] = s;
+        pp_[tid] = p;
+        qq_[tid] = q < k ? q : -1;
+      }
+      __syncthreads();
+      // rows p, q of G <- J^T G
+      for (int idx = tid; idx < npair * k; idx += 256) {
+        const int x = idx / k, j = idx % k;
+        const int q = qq_[x];
+        if (q < 0) continue;
+        const int p = pp_[x];
+        const double c = cs_[x], s = sn_[x];
+        const double gp = G[p * LD + j], gq = G[q * LD + j];
+        G[p * LD + j] = c * gp - s * gq;
+        G[q * LD + j] = s * gp + c * gq;
+      }
+      __syncthreads();
+      // columns p, q of G and V <- (.) J
+      for (int idx = tid; idx < npair * k; idx += 256) {
+        const int x = idx / k, j = idx % k;
+        const int q = qq_[x];
+        if (q < 0) continue;
+        const int p = pp_[x];
+        const double c = cs_[x], s = sn_[x];
+        const double hp = G[j * LD + p], hq = G[j * LD + q];
+        G[j * LD + p] = c * hp - s * hq;
+        G[j * LD + q] = s * hp + c * hq;
+        const double vp = V[j * LD + p], vq = V[j * LD + q];
+        V[j * LD + p] = c * vp - s * vq;
+        V[j * LD + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+
+  // Eigenvalues; rank check; sum of singular values of A_i.
+  double lmax = 0.0, lmin = 1e300, ssq = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double l = G[j * LD + j];
+    lmax = fmax(lmax, l);
+    lmin = fmin(lmin, l);
+  }
+  const bool rank_ok = lmin > 1e-13 * lmax && lmax > 0.0;
+  for (int j = 0; j < k; ++j) ssq += sqrt(fmax(G[j * LD + j], 0.0));
+  __syncthreads();
+  // P = V diag(lambda^-1/2) V^T  (written zero padded to KP x KP)
+  double* P = a.P64 + (int64_t)i * KP * KP;
+  for (int idx = tid; idx < KP * KP; idx += 256) {
+    const int p = idx / KP, q = idx % KP;
+    double s = 0.0;
+    if (p < k && q < k && rank_ok) {
+      for (int j = 0; j < k; ++j)
+        s += V[p * LD + j] * V[q * LD + j] / sqrt(G[j * LD + j]);
+    }
+    P[idx] = s;
+  }
+  if (tid == 0) {
+    const double t = (double)a.t;
+    const double r = (a.c[i] - 2.0 * ssq + t * a.sc->tau_cur) / (t * su.v);
+    a.rho2[i] = rank_ok ? r : 1.0;
+    if (!rank_ok && a.sc->status == 0) a.sc->status = 4;  // SRM_E_RANK
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Results: W_i = A_i P_i (deferred polar factor) and the transform
+// S_new = W_i^T (X_new - mu_i 1^T) = P_i A_i^T (X_new - mu_i 1^T).
+// ---------------------------------------------------------------------------
+template <int KP>
+__device__ __forceinline__ double a_elem(const void* ah, const void* al,
+                                         int prec, int64_t R, int b) {
+  constexpr int NB = KP / 16;
+  const int64_t rb = R >> 5;
+  const int rr = (int)(R & 31);
+  const int g = (rr & 15) >> 2, e = ((rr >> 4) << 2) + (rr & 3);
+  const int lane = (b & 15) + 16 * g;
+  const int64_t o = ((rb * NB + (b >> 4)) * 64 + lane) * 8 + e;
+  if (prec == P_FP32) return (double)((const float*)ah)[o];
+  return (double)bf2f(((const uint16_t*)ah)[o]) +
+         (double)bf2f(((const uint16_t*)al)[o]);
+}
+
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_get_w(WArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.v * a.k) return;
+  const int64_t r = idx / a.k;
+  const int j = (int)(idx % a.k);
+  double s = 0.0;
+  for (int b = 0; b < a.k; ++b)
+    s += a_elem<KP>(a.ah, a.al, a.prec, a.row0 + r, b) * a.P[b * KP + j];
+  a.dst[idx] = (float)s;
+}
+
+
+// Partial Z[:, cols] = sum over a row split of A[r, :]^T (x_r - mu_r).
+template <int KP>
+__global__ __launch_bounds__(256) void k_transform_part(TArgs a) {
+  constexpr int NJ = KP / 4;
+  const int c = threadIdx.x & 63, jr = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + c;
+  const int r0 = blockIdx.y * a.rows_per_split;
+  int r1 = r0 + a.rows_per_split;
+  if (r1 > a.v) r1 = a.v;
+  float acc[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) acc[u] = 0.f;
+  if (col < a.tn) {
+    for (int r = r0; r < r1; ++r) {
+      const float x = a.X[(int64_t)r * a.ldx + col] - (float)a.mu[a.row0 + r];
+#pragma unroll
+      for (int u = 0; u < NJ; ++u)
+        acc[u] += (float)a_elem<KP>(a.ah, a.al, a.prec, a.row0 + r, jr + 4 * u) * x;
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+      a.part[((int64_t)blockIdx.y * KP + jr + 4 * u) * a.tn + col] = acc[u];
+  }
+}
+
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_transform_fin(TFArgs a) {
+  __shared__ double Zs[KP][64];
+  const int c = threadIdx.x & 63, jr = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + c;
+  for (int j = jr; j < KP; j += 4) {
+    double s = 0.0;
+    if (col < a.tn)
+      for (int sp = 0; sp < a.nsplit; ++sp)
+        s += (double)a.part[((int64_t)sp * KP + j) * a.tn + col];
+    Zs[j][c] = s;
+  }
+  __syncthreads();
+  if (col >= a.tn) return;
+  for (int j = jr; j < a.k; j += 4) {
+    double s = 0.0;
+    for (int b = 0; b < a.k; ++b) s += a.P[j * KP + b] * Zs[b][c];
+    a.out[(int64_t)j * a.ldo + col] = (float)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (template dispatch on K padding and storage format).
+// ---------------------------------------------------------------------------
+#define SRM_KP_SWITCH(KPV, ...)                          \
+  switch (KPV) {                                         \
+    case 16: { constexpr int KP = 16; __VA_ARGS__; } break;  \
+    case 32: { constexpr int KP = 32; __VA_ARGS__; } break;  \
+    case 48: { constexpr int KP = 48; __VA_ARGS__; } break;  \
+    case 64: { constexpr int KP = 64; __VA_ARGS__; } break;  \
+    case 80: { constexpr int KP = 80; __VA_ARGS__; } break;  \
+    case 96: { constexpr int KP = 96; __VA_ARGS__; } break;  \
+    case 112: { constexpr int KP = 112; __VA_ARGS__; } break; \
+    case 128: { constexpr int KP = 128; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                \
+  }
+
+#define SRM_PREC_SWITCH(PV, ...)                                  \
+  switch (PV) {                                                   \
+    case P_FP32: { constexpr int PR = P_FP32; __VA_ARGS__; } break;   \
+    case P_BF16: { constexpr int PR = P_BF16; __VA_ARGS__; } break;   \
+    case P_BF16X2: { constexpr int PR = P_BF16X2; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+hipError_t launch_convert(hipStream_t st, int grid, const ConvertArgs& a) {
+  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_rowsum(hipStream_t st, int N, const double* rowc,
+                         const Subject* subj, double* c) {
+  hipLaunchKernelGGL(k_rowsum, dim3(N), dim3(256), 0, st, rowc, subj, c);
+  return hipGetLastError();
+}
+hipError_t launch_mphase(hipStream_t st, int kp, int prec, int grid,
+                         const MArgs& a) {
+  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
+      hipLaunchKernelGGL((k_mphase<KP, PR>), dim3(grid), dim3(256), 0, st, a)));
+  return hipGetLastError();
+}
+hipError_t launch_ephase(hipStream_t st, int kp, int prec, int grid,
+                         const EArgs& a) {
+  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
+      hipLaunchKernelGGL((k_ephase<KP, PR>), dim3(grid), dim3(256), 0, st, a)));
+  return hipGetLastError();
+}
+int ereduce_ct(int kp) { return kp <= 64 ? 64 : (kp <= 96 ? 32 : 16); }
+hipError_t launch_ereduce(hipStream_t st, int kp, int ncol, int ngrp,
+                          const RArgs& a) {
+  dim3 grid(ncol, ngrp);
+  switch (ereduce_ct(kp)) {
+    case 64: SRM_KP_SWITCH(kp, if constexpr (KP <= 64) hipLaunchKernelGGL(
+                 (k_ereduce<KP, 64>), grid, dim3(256), 0, st, a)); break;
+    case 32: SRM_KP_SWITCH(kp, if constexpr (KP > 64 && KP <= 96) hipLaunchKernelGGL(
+                 (k_ereduce<KP, 32>), grid, dim3(256), 0, st, a)); break;
+    default: SRM_KP_SWITCH(kp, if constexpr (KP > 96) hipLaunchKernelGGL(
+                 (k_ereduce<KP, 16>), grid, dim3(256), 0, st, a)); break;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_post_prep(hipStream_t st, int kp, const PrepArgs& a) {
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_post_prep<KP>), dim3(1), dim3(256), 0, st, a));
+  return hipGetLastError();
+}
+hipError_t launch_post_s(hipStream_t st, int kp, int prec, int nblk,
+                         const SArgs& a) {
+  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
+      hipLaunchKernelGGL((k_post_s<KP, PR>), dim3(nblk), dim3(256), 0, st, a)));
+  return hipGetLastError();
+}
+hipError_t launch_post_fin(hipStream_t st, int kp, const FinArgs& a) {
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_post_fin<KP>), dim3(1), dim3(256), 0, st, a));
+  return hipGetLastError();
+}
+hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
+  hipLaunchKernelGGL(k_copy_state, dim3(64), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_polar<KP>), dim3(N), dim3(256), 0, st, a));
+  return hipGetLastError();
+}
+hipError_t launch_get_w(hipStream_t st, int kp, const WArgs& a) {
+  const int64_t n = (int64_t)a.v * a.k;
+  const int grid = (int)((n + 255) / 256);
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_get_w<KP>), dim3(grid), dim3(256), 0, st, a));
+  return hipGetLastError();
+}
+hipError_t launch_transform(hipStream_t st, int kp, int nsplit, const TArgs& a,
+                            const TFArgs& f) {
+  const int ncol = (int)((a.tn + 63) / 64);
+  SRM_KP_SWITCH(kp,
+      hipLaunchKernelGGL((k_transform_part<KP>), dim3(ncol, nsplit), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_transform_fin<KP>), dim3(ncol), dim3(256), 0, st, f));
+  return hipGetLastError();
+}
+
+hipError_t occupancy_mphase(int kp, int prec, int* blocks) {
+  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_mphase<KP, PR>, 256, 0)));
+  return hipErrorInvalidValue;
+}
+hipError_t occupancy_ephase(int kp, int prec, int* blocks) {
+  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase<KP, PR>, 256, 0)));
+  return hipErrorInvalidValue;
+}
+
+}  // namespace srm

@@ -1,0 +1,187 @@
+"""Device path vs the FP64 oracle, element by element on the same seeded inputs.
+
+Bars: relative Frobenius error <= 1e-4 on S (after the Procrustes rotation the
+model cannot identify) and on the projectors W_i W_i^T for FP32 storage,
+<= 1e-3 for BF16 hi+lo storage; plain BF16 storage is held to 1e-3 against
+the oracle fed the same rounded values.  Every test calls the C-ABI through
+the Python binding.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_04647_amd import synth
+
+from _parity import compare, proj_err, stored_values
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp32": 1e-4, "bf16x2": 1e-3, "bf16": 1e-3}
+
+
+def _srm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_04647_amd import srm
+    return srm
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run_case(name, w, prec, seed=0, n_iter=None):
+    srm = _srm()
+    n_iter = w.n_iter if n_iter is None else n_iter
+    d = synth.generate(w, seed=seed)
+    _say(f"[case] {name} prec={prec} N={w.n_subjects} v={[x.shape[0] for x in d['X']][:6]} "
+         f"t={w.t} k={w.k} iters={n_iter}")
+    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"])
+    g.fit(n_iter)
+    if prec == "bf16":
+        Xq = [stored_values(x, prec) for x in d["X"]]
+        ora = oracle.em_fit(Xq, w.k, n_iter, d["W0"], final_loglik=True, demeaned=True)
+    else:
+        ora = oracle.em_fit(d["X"], w.k, n_iter, d["W0"], final_loglik=True)
+    e = compare(g, ora, w.n_subjects)
+    _say(f"[errors] {name}/{prec}: " + ", ".join(f"{k}={v:.2e}" for k, v in e.items()
+                                                 if k != "ll_gpu"))
+    return g, ora, e, d
+
+
+CASES = {
+    "tiny": synth.WORKLOADS["tiny"],
+    # ragged voxel counts, k not a multiple of 16, t not a multiple of 64
+    "ragged": synth.Workload("ragged", 5, 33, 250, 70, 7, 8),
+    # many row ranges and slices crossing subjects
+    "slices": synth.Workload("slices", 6, 3000, 9000, 300, 20, 6,
+                             sigma_lo=0.5, sigma_hi=2.0),
+    # k = 100: the k x k work that does not fit in LDS
+    "k100": synth.Workload("k100", 3, 300, 420, 150, 100, 4,
+                           sigma_lo=0.5, sigma_hi=2.0, rho_lo=0.3, rho_hi=0.6),
+    "k128": synth.Workload("k128", 2, 200, 260, 140, 128, 3, rho_lo=0.3, rho_hi=0.6),
+    # single subject; smallest k
+    "n1k1": synth.Workload("n1k1", 1, 40, 40, 16, 1, 5),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "bf16"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_parity(case, prec):
+    if case in ("k128", "n1k1") and prec == "bf16":
+        pytest.skip("covered by the other formats")
+    g, ora, e, _ = _run_case(case, CASES[case], prec)
+    bar = BAR[prec]
+    assert e["S"] <= bar and e["W"] <= bar
+    assert e["rho2"] <= bar and e["Sigma_s"] <= bar
+    assert e["ll"] <= 1e-6 if prec == "fp32" else e["ll"] <= 1e-4
+    assert e["orth"] <= (1e-5 if prec == "fp32" else 1e-4)
+    ll = e["ll_gpu"]
+    assert len(ll) == CASES[case].n_iter + 1
+    assert np.all(np.diff(ll) >= -1e-6 * np.abs(ll[:-1]))
+    g.close()
+
+
+def test_bf16_plain_against_original_data_reports_quantisation_error():
+    """Plain BF16 storage is within the bar of the oracle fed the rounded data
+    and, on the original data, within the rounding floor (~u/sqrt(3))."""
+    w = CASES["tiny"]
+    g, ora, e, d = _run_case("tiny", w, "bf16")
+    ref = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    eW = max(proj_err(ref["W"][i], g.W(i).cpu().numpy()) for i in range(w.n_subjects))
+    _say(f"[errors] bf16 vs oracle on original X: W={eW:.2e}")
+    assert eW < 3e-2
+
+
+def test_fit_is_deterministic_and_resumable():
+    srm = _srm()
+    w = CASES["slices"]
+    d = synth.generate(w, seed=5)
+    a = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"])
+    a.fit(6)
+    b = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"])
+    b.fit(3)
+    b.fit(3)
+    c = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=srm.SRM_NO_GRAPH)
+    for _ in range(6):
+        c.em_step()
+    for x in (b, c):
+        assert np.array_equal(a.S().cpu().numpy(), x.S().cpu().numpy())
+        assert np.array_equal(a.rho2(), x.rho2())
+        assert np.array_equal(a.loglik(), x.loglik())
+        assert np.array_equal(a.W(2).cpu().numpy(), x.W(2).cpu().numpy())
+    assert a.iterations() == 6
+
+
+def test_em_step_returns_entering_loglik():
+    srm = _srm()
+    w = CASES["tiny"]
+    d = synth.generate(w, seed=1)
+    g = srm.SRM(d["X"], w.k, prec="fp32", W0=d["W0"])
+    ll0 = g.em_step()
+    ll1 = g.em_step()
+    ora = oracle.em_fit(d["X"], w.k, 2, d["W0"])
+    assert abs(ll0 - ora["ll"][0]) <= 1e-7 * abs(ora["ll"][0])
+    assert abs(ll1 - ora["ll"][1]) <= 1e-7 * abs(ora["ll"][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_transform_matches_oracle_projection(prec):
+    """S_new = W_i^T (X_new - mu_i 1^T) (Sec. II-A) for held-out samples."""
+    srm = _srm()
+    w = CASES["ragged"]
+    d = synth.generate(w, seed=2)
+    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"])
+    g.fit(w.n_iter)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    rng = np.random.default_rng(0)
+    for i in (0, 3):
+        Xn = rng.standard_normal((d["X"][i].shape[0], 131)).astype(np.float32)
+        out = g.transform(i, Xn).cpu().numpy().astype(np.float64)
+        ref = ora["W"][i].T @ (Xn.astype(np.float64) - ora["mu"][i][:, None])
+        # compare in the rotation-free form W W^T (x - mu)
+        lhs = g.W(i).cpu().numpy().astype(np.float64) @ out
+        rhs = ora["W"][i] @ ref
+        err = np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
+        _say(f"[errors] transform {prec} subject {i}: {err:.2e}")
+        assert err <= BAR[prec]
+        mu = g.mu(i).cpu().numpy()
+        assert np.allclose(mu, ora["mu"][i], rtol=0, atol=1e-6)
+
+
+def test_nonfinite_input_is_rejected():
+    srm = _srm()
+    w = CASES["tiny"]
+    d = synth.generate(w, seed=0)
+    d["X"][1][7, 3] = np.nan
+    with pytest.raises(srm.SRMError) as ei:
+        srm.SRM(d["X"], w.k, prec="fp32", W0=d["W0"])
+    assert ei.value.status == srm.SRM_E_NONFINITE
+
+
+def test_rank_deficient_subject_raises():
+    """Reading R10: an all-zero subject gives A_i = 0, which has no polar factor."""
+    srm = _srm()
+    w = CASES["tiny"]
+    d = synth.generate(w, seed=0)
+    d["X"][2][:] = 1.0  # constant rows demean to exactly zero
+    g = srm.SRM(d["X"], w.k, prec="fp32", W0=d["W0"])
+    with pytest.raises(srm.SRMError) as ei:
+        g.fit(2)
+    assert ei.value.status == srm.SRM_E_RANK
+
+
+def test_getters_before_first_iteration():
+    srm = _srm()
+    w = CASES["tiny"]
+    d = synth.generate(w, seed=0)
+    g = srm.SRM(d["X"], w.k, prec="fp32", W0=d["W0"])
+    with pytest.raises(srm.SRMError) as ei:
+        g.W(0)
+    assert ei.value.status == srm.SRM_E_STATE
+    assert len(g.loglik()) == 1
