@@ -122,6 +122,27 @@ srm_status srm_em_step(srm_ctx *ctx, double *loglik);
  * without host synchronisation; the stream is synchronised once at the end. */
 srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
 
+/* Kernel phases of one iteration, in launch order (indices of srm_profile):
+ *  SRM_PHASE_MPHASE    A = Xhat S^T over all subjects (Eq. 4, A_i)
+ *  SRM_PHASE_EPHASE    per-slice A^T Xhat and A^T A (Eq. 10 partials, Eq. 4 Gram)
+ *  SRM_PHASE_POLAR     per-subject FP64 Jacobi polar factor and rho_i^2 (Eq. 4-5)
+ *  SRM_PHASE_EREDUCE   Y = sum_i rho_i^-2 W_i^T Xhat_i (Eq. 10 reduction)
+ *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11) */
+enum {
+  SRM_PHASE_MPHASE = 0,
+  SRM_PHASE_EPHASE = 1,
+  SRM_PHASE_POLAR = 2,
+  SRM_PHASE_EREDUCE = 3,
+  SRM_PHASE_POSTERIOR = 4,
+  SRM_NPHASE = 5
+};
+
+/* Runs n_iter iterations like srm_fit but with direct kernel launches, each
+ * kernel bracketed by HIP events on the context's stream, and adds each
+ * phase's measured milliseconds into ms[SRM_NPHASE] (host; zeroed first).
+ * Synchronises after every iteration; meant for measurement, not speed. */
+srm_status srm_profile(srm_ctx *ctx, int32_t n_iter, double *ms);
+
 /* Project new samples of subject i into the shared space (Sec. II-A:
  * s = W_i^T (x - mu_i)):  S_out = W_i^T (X_new - mu_i 1^T).
  *   X_new: device, v_i x t_new float32, row stride t_new (t_new >= 1).

@@ -222,6 +222,9 @@ struct srm_ctx {
   bool graph_ok = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // Per-kernel HIP events for srm_profile (direct launches only).
+  bool profiling = false;
+  hipEvent_t ev[2 * SRM_NPHASE] = {};
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -346,6 +349,18 @@ struct Ptrs {
   void *xh, *xl, *ah, *al, *shc, *slc, *shn, *sln;
 };
 
+// Brackets one kernel of phase ph with HIP events when profiling.
+struct Phase {
+  srm_ctx* c;
+  int ph;
+  Phase(srm_ctx* cc, int p) : c(cc), ph(p) {
+    if (c->profiling) (void)hipEventRecord(c->ev[2 * ph], c->stream);
+  }
+  ~Phase() {
+    if (c->profiling) (void)hipEventRecord(c->ev[2 * ph + 1], c->stream);
+  }
+};
+
 Ptrs ptrs(const srm_ctx* c) {
   const Plan& p = c->p;
   Ptrs q;
@@ -370,20 +385,29 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar) {
   EArgs ea{q.xh, q.xl, q.ah, q.al, c->at<Slice>(p.o_slices),
            c->at<int32_t>(p.o_rs), c->at<float>(p.o_zpart), c->at<float>(p.o_gpart),
            p.ldt, p.npanel, with_polar ? 1 : 0};
-  if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
+  {
+    Phase ph(c, SRM_PHASE_EPHASE);
+    if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
+  }
   if (with_polar) {
     QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_c),
              c->at<double>(p.o_rho2), c->at<double>(p.o_p64), c->at<double>(p.o_polwork),
              c->at<Scalars>(p.o_sc), p.k, p.t};
+    Phase ph(c, SRM_PHASE_POLAR);
     if ((e = launch_polar(st, p.KP, p.N, qa)) != hipSuccess) return e;
   }
   RArgs ra{c->at<float>(p.o_zpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_p64),
            c->at<double>(p.o_rho2), c->at<double>(p.o_ygrp), p.N, p.gsub, p.ldt};
-  if ((e = launch_ereduce(st, p.KP, p.ncol_r, p.ngrp, ra)) != hipSuccess) return e;
+  {
+    Phase ph(c, SRM_PHASE_EREDUCE);
+    if ((e = launch_ereduce(st, p.KP, p.ncol_r, p.ngrp, ra)) != hipSuccess) return e;
+  }
   PrepArgs pa{c->at<double>(p.o_rho2), c->at<double>(p.o_c), c->at<Subject>(p.o_subj),
               c->at<double>(p.o_sigcur), c->at<double>(p.o_M), c->at<double>(p.o_prepwork),
               c->at<Scalars>(p.o_sc), p.N, p.k};
-  if ((e = launch_post_prep(st, p.KP, pa)) != hipSuccess) return e;
+  {
+    Phase ph(c, SRM_PHASE_POSTERIOR);
+    if ((e = launch_post_prep(st, p.KP, pa)) != hipSuccess) return e;
   SArgs sa{c->at<double>(p.o_ygrp), c->at<double>(p.o_M), c->at<double>(p.o_s64new),
            q.shn, q.sln, c->at<double>(p.o_sspart), c->at<double>(p.o_trpart),
            p.ngrp, p.k, p.t, p.ldt};
@@ -394,6 +418,7 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar) {
              c->at<double>(p.o_signew), c->at<double>(p.o_ll), c->at<Scalars>(p.o_sc),
              p.nblk_s, p.k, p.t, Vtot};
   return launch_post_fin(st, p.KP, fa);
+  }
 }
 
 // One EM iteration: M-step on the current posterior, then the next E-step.
@@ -408,7 +433,10 @@ hipError_t enqueue_iteration(srm_ctx* c) {
               (int64_t)p.KP * p.ldt, (int64_t)(p.srec_bytes / 16), p.KP * p.KP};
   if ((e = launch_copy_state(st, ca)) != hipSuccess) return e;
   MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, p.total_rows, c->m_ntiles, c->m_tpw};
-  if ((e = launch_mphase(st, p.KP, p.prec, c->m_grid, ma)) != hipSuccess) return e;
+  {
+    Phase ph(c, SRM_PHASE_MPHASE);
+    if ((e = launch_mphase(st, p.KP, p.prec, c->m_grid, ma)) != hipSuccess) return e;
+  }
   return enqueue_estep(c, true);
 }
 
@@ -607,6 +635,31 @@ srm_status srm_fit(srm_ctx* c, int32_t n_iter, double* loglik) {
   return SRM_OK;
 }
 
+srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (n_iter < 0 || !ms) return fail(SRM_E_ARG, "invalid argument");
+  for (int i = 0; i < SRM_NPHASE; ++i) ms[i] = 0.0;
+  for (int i = 0; i < 2 * SRM_NPHASE; ++i)
+    if (!c->ev[i]) HIP_OR_FAIL(hipEventCreate(&c->ev[i]));
+  c->profiling = true;
+  for (int it = 0; it < n_iter; ++it) {
+    const hipError_t e = enqueue_iteration(c);
+    if (e != hipSuccess) {
+      c->profiling = false;
+      return fail(SRM_E_HIP, "launch failed: %s", hipGetErrorString(e));
+    }
+    ++c->iters;
+    HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+    for (int ph = 0; ph < SRM_NPHASE; ++ph) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, c->ev[2 * ph], c->ev[2 * ph + 1]) == hipSuccess) ms[ph] += t;
+    }
+  }
+  c->profiling = false;
+  Scalars sc{};
+  return read_scalars(c, &sc);
+}
+
 srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_new,
                          float* S_out) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");
@@ -729,6 +782,8 @@ const char* srm_last_error(void) { return g_err.c_str(); }
 void srm_free(srm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

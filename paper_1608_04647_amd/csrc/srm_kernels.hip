@@ -426,6 +426,8 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
                 gacc[p >> 2] = mfma_bf16(ah[j1], ah[j2], gacc[p >> 2]);
                 gacc[p >> 2] = mfma_bf16(ah[j1], al[j2], gacc[p >> 2]);
                 gacc[p >> 2] = mfma_bf16(al[j1], ah[j2], gacc[p >> 2]);
+                // lo*lo too: its error would scale with cond(A^T A) in W^T W.
+                gacc[p >> 2] = mfma_bf16(al[j1], al[j2], gacc[p >> 2]);
               }
         }
       }

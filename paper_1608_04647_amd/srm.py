@@ -45,6 +45,7 @@ _sigs = {
     "srm_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(SrmDesc), _P, _P, _P, _SZ]),
     "srm_em_step": (ctypes.c_int, [_P, _DP]),
     "srm_fit": (ctypes.c_int, [_P, _I32, _DP]),
+    "srm_profile": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_transform": (ctypes.c_int, [_P, _I32, _P, _I64, _P]),
     "srm_get_w": (ctypes.c_int, [_P, _I32, _P]),
     "srm_get_s": (ctypes.c_int, [_P, _P]),
@@ -151,6 +152,15 @@ class SRM:
         ll = np.zeros(max(n_iter, 1))
         _check(_lib.srm_fit(self._ctx, int(n_iter), ll.ctypes.data_as(_DP)))
         return ll[:n_iter]
+
+    PHASES = ("mphase", "ephase", "polar", "ereduce", "posterior")
+
+    def profile(self, n_iter: int) -> dict:
+        """Milliseconds per kernel phase summed over n_iter iterations, from HIP
+        events on the library's stream (direct launches)."""
+        ms = np.zeros(len(self.PHASES))
+        _check(_lib.srm_profile(self._ctx, int(n_iter), ms.ctypes.data_as(_DP)))
+        return dict(zip(self.PHASES, ms.tolist()))
 
     def em_step(self) -> float:
         ll = ctypes.c_double()

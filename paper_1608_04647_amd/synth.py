@@ -183,3 +183,26 @@ def iter_subjects(w: Workload, seed: int = 0, threads: Optional[int] = None,
                 pending.append(ex.submit(one, nxt))
                 nxt += 1
             yield r
+
+
+def to_device(w: Workload, seed: int = 0, device=None, threads: Optional[int] = None,
+              with_w0: bool = True):
+    """Generate the workload straight into one float32 device buffer.
+
+    Returns (list of per-subject torch views v_i x t, list of W0_i host arrays
+    or None, Globals).  Subjects are drawn on a thread pool and copied one by
+    one, so host memory holds only a few subjects of X at a time."""
+    import torch
+    g = draw_globals(w, seed)
+    dev = device or torch.device("cuda")
+    total = int(g.v.sum())
+    buf = torch.empty((total, w.t), dtype=torch.float32, device=dev)
+    offs = np.concatenate([[0], np.cumsum(g.v)]).astype(np.int64)
+    w0 = [None] * w.n_subjects if with_w0 else None
+    for i, X, W0 in iter_subjects(w, seed, threads, with_w0=with_w0):
+        buf[offs[i]:offs[i + 1]].copy_(torch.from_numpy(X))
+        if with_w0:
+            w0[i] = W0
+    torch.cuda.synchronize()
+    views = [buf[offs[i]:offs[i + 1]] for i in range(w.n_subjects)]
+    return views, w0, g
