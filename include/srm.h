@@ -75,8 +75,9 @@ enum {
   SRM_NO_GRAPH = 1u,    /* launch each iteration's kernels directly instead of
                            replaying one captured hipGraph                     */
   SRM_NO_W0_CHECK = 2u, /* skip the host check that W0_i^T W0_i = I            */
-  SRM_TWO_PASS = 4u     /* force two passes over Xhat per iteration even where a
-                           one-pass sweep is available                         */
+  SRM_TWO_PASS = 4u     /* use the two-pass sweep (A = Xhat S^T to HBM, then
+                           A^T Xhat) even where the fused one-pass sweep applies
+                           (BF16 forms with k <= 64 and t <= 512)              */
 };
 
 typedef struct {
@@ -127,14 +128,17 @@ srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
  *  SRM_PHASE_EPHASE    per-slice A^T Xhat and A^T A (Eq. 10 partials, Eq. 4 Gram)
  *  SRM_PHASE_POLAR     per-subject FP64 Jacobi polar factor and rho_i^2 (Eq. 4-5)
  *  SRM_PHASE_EREDUCE   Y = sum_i rho_i^-2 W_i^T Xhat_i (Eq. 10 reduction)
- *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11) */
+ *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11)
+ *  SRM_PHASE_FUSED     one-pass sweep forming A, A^T Xhat and A^T A together
+ *                      (replaces MPHASE + EPHASE where it applies) */
 enum {
   SRM_PHASE_MPHASE = 0,
   SRM_PHASE_EPHASE = 1,
   SRM_PHASE_POLAR = 2,
   SRM_PHASE_EREDUCE = 3,
   SRM_PHASE_POSTERIOR = 4,
-  SRM_NPHASE = 5
+  SRM_PHASE_FUSED = 5,
+  SRM_NPHASE = 6
 };
 
 /* Runs n_iter iterations like srm_fit but with direct kernel launches, each

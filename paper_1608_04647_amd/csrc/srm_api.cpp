@@ -32,6 +32,8 @@ hipError_t launch_polar(hipStream_t, int, int, const QArgs&);
 hipError_t launch_get_w(hipStream_t, int, const WArgs&);
 hipError_t launch_transform(hipStream_t, int, int, const TArgs&, const TFArgs&);
 hipError_t occupancy_mphase(int, int, int*);
+bool fused_supported(int kp, int prec, int64_t ldt);
+hipError_t launch_fused(hipStream_t, int, int, int64_t, int, const FusedArgs&);
 hipError_t occupancy_ephase(int, int, int*);
 }  // namespace srm
 
@@ -64,12 +66,15 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // (two 4-wave workgroups per CU).  Fixed so that the workspace size does not
 // depend on a device query.
 constexpr int kEphaseWGs = 512;
+// Fused sweep: 8-wave workgroups, about one per CU; two equal rounds.
+constexpr int kFusedWGs = 512;
 constexpr int kReduceWGs = 512;
 
 struct Plan {
   int N = 0, k = 0, KP = 0, NB = 0, prec = 0;
   int64_t t = 0, ldt = 0, total_rows = 0;
   int npanel = 0, nranges = 0, nslices = 0;
+  bool fused = false;
   int rct = 0, ncol_r = 0, gsub = 0, ngrp = 0;
   int nblk_s = 0;
   std::vector<Subject> subj;
@@ -118,6 +123,9 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.prec = d->prec;
   p.t = d->t;
   p.ldt = round_up(d->t, kColPad);
+  // The one-pass sweep runs whole 128-TR groups (pairs of 64-TR waves).
+  if (fused_supported(p.KP, p.prec, round_up(d->t, 128)) && !(d->flags & SRM_TWO_PASS))
+    p.ldt = round_up(d->t, 128);
   p.subj.resize(p.N);
   int64_t row = 0;
   for (int i = 0; i < p.N; ++i) {
@@ -129,8 +137,10 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.total_rows = row;
   // E-phase: equal row ranges (multiples of 32 rows) split at subject ends.
   p.npanel = (int)((p.ldt + 255) / 256);
+  p.fused = fused_supported(p.KP, p.prec, p.ldt) && !(d->flags & SRM_TWO_PASS);
   const int64_t nblk32 = p.total_rows / 32;
-  p.nranges = (int)std::max<int64_t>(1, std::min<int64_t>(nblk32, kEphaseWGs / p.npanel));
+  p.nranges = (int)std::max<int64_t>(
+      1, std::min<int64_t>(nblk32, p.fused ? kFusedWGs : kEphaseWGs / p.npanel));
   p.range_slice.assign(p.nranges + 1, 0);
   p.slices.clear();
   int si = 0;
@@ -220,10 +230,12 @@ struct srm_ctx {
   int64_t m_tpw = 0, m_ntiles = 0;
   int iters = 0;
   bool graph_ok = false;
+  bool a_valid = true;  // A records in HBM match the current S (two-pass)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // Per-kernel HIP events for srm_profile (direct launches only).
   bool profiling = false;
+  bool recorded[SRM_NPHASE] = {};
   hipEvent_t ev[2 * SRM_NPHASE] = {};
 
   template <class T>
@@ -354,7 +366,10 @@ struct Phase {
   srm_ctx* c;
   int ph;
   Phase(srm_ctx* cc, int p) : c(cc), ph(p) {
-    if (c->profiling) (void)hipEventRecord(c->ev[2 * ph], c->stream);
+    if (c->profiling) {
+      (void)hipEventRecord(c->ev[2 * ph], c->stream);
+      c->recorded[ph] = true;
+    }
   }
   ~Phase() {
     if (c->profiling) (void)hipEventRecord(c->ev[2 * ph + 1], c->stream);
@@ -377,7 +392,7 @@ Ptrs ptrs(const srm_ctx* c) {
 
 // E-phase + reduction + posterior: from the current A, P, rho produce the
 // E-step's S (into the "new" buffers), Sigma_s_new, tau_new and one LL.
-hipError_t enqueue_estep(srm_ctx* c, bool with_polar) {
+hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
   const Plan& p = c->p;
   const Ptrs q = ptrs(c);
   hipStream_t st = c->stream;
@@ -385,7 +400,7 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar) {
   EArgs ea{q.xh, q.xl, q.ah, q.al, c->at<Slice>(p.o_slices),
            c->at<int32_t>(p.o_rs), c->at<float>(p.o_zpart), c->at<float>(p.o_gpart),
            p.ldt, p.npanel, with_polar ? 1 : 0};
-  {
+  if (stream_pass) {
     Phase ph(c, SRM_PHASE_EPHASE);
     if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
   }
@@ -432,12 +447,23 @@ hipError_t enqueue_iteration(srm_ctx* c) {
               c->at<double>(p.o_signew), c->at<double>(p.o_sigcur), c->at<Scalars>(p.o_sc),
               (int64_t)p.KP * p.ldt, (int64_t)(p.srec_bytes / 16), p.KP * p.KP};
   if ((e = launch_copy_state(st, ca)) != hipSuccess) return e;
-  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, p.total_rows, c->m_ntiles, c->m_tpw};
+  if (p.fused) {
+    FusedArgs fa{q.xh, q.xl, q.shc, q.slc, c->at<Slice>(p.o_slices), c->at<int32_t>(p.o_rs),
+                 c->at<float>(p.o_zpart), c->at<float>(p.o_gpart), p.ldt};
+    {
+      Phase ph(c, SRM_PHASE_FUSED);
+      if ((e = launch_fused(st, p.KP, p.prec, p.ldt, p.nranges, fa)) != hipSuccess) return e;
+    }
+    c->a_valid = false;
+    return enqueue_estep(c, true, /*stream_pass=*/false);
+  }
+  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, 0, p.total_rows, c->m_ntiles, c->m_tpw};
   {
     Phase ph(c, SRM_PHASE_MPHASE);
     if ((e = launch_mphase(st, p.KP, p.prec, c->m_grid, ma)) != hipSuccess) return e;
   }
-  return enqueue_estep(c, true);
+  c->a_valid = true;
+  return enqueue_estep(c, true, /*stream_pass=*/true);
 }
 
 srm_status run_iterations(srm_ctx* c, int n) {
@@ -603,7 +629,7 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
   if (chk.nonfinite) return bail(fail(SRM_E_NONFINITE, "X contains NaN or Inf"));
 
   // First E-step with W_i = W0_i (P = I), rho^2 = 1, Sigma_s = I.
-  if (enqueue_estep(c, false) != hipSuccess)
+  if (enqueue_estep(c, false, true) != hipSuccess)
     return bail(fail(SRM_E_HIP, "first E-step launch failed"));
   s = read_scalars(c, &chk);
   if (s != SRM_OK) return bail(s);
@@ -635,6 +661,20 @@ srm_status srm_fit(srm_ctx* c, int32_t n_iter, double* loglik) {
   return SRM_OK;
 }
 
+// The fused sweep never writes A = Xhat S^T to HBM; recompute subject i's
+// rows from the current S before W_i = A_i P_i is formed.
+static srm_status ensure_a(srm_ctx* c, int i) {
+  if (c->a_valid) return SRM_OK;
+  const Plan& p = c->p;
+  const Ptrs q = ptrs(c);
+  const Subject& su = p.subj[i];
+  const int64_t nt = (su.vp + 63) / 64;
+  const int64_t tpw = 4;
+  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, su.row0, su.row0 + su.vp, nt, tpw};
+  HIP_OR_FAIL(launch_mphase(c->stream, p.KP, p.prec, (int)((nt + tpw - 1) / tpw), ma));
+  return SRM_OK;
+}
+
 srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");
   if (n_iter < 0 || !ms) return fail(SRM_E_ARG, "invalid argument");
@@ -643,6 +683,7 @@ srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
     if (!c->ev[i]) HIP_OR_FAIL(hipEventCreate(&c->ev[i]));
   c->profiling = true;
   for (int it = 0; it < n_iter; ++it) {
+    for (auto& r : c->recorded) r = false;
     const hipError_t e = enqueue_iteration(c);
     if (e != hipSuccess) {
       c->profiling = false;
@@ -651,8 +692,10 @@ srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
     ++c->iters;
     HIP_OR_FAIL(hipStreamSynchronize(c->stream));
     for (int ph = 0; ph < SRM_NPHASE; ++ph) {
+      if (!c->recorded[ph]) continue;
       float t = 0.f;
-      if (hipEventElapsedTime(&t, c->ev[2 * ph], c->ev[2 * ph + 1]) == hipSuccess) ms[ph] += t;
+      HIP_OR_FAIL(hipEventElapsedTime(&t, c->ev[2 * ph], c->ev[2 * ph + 1]));
+      ms[ph] += t;
     }
   }
   c->profiling = false;
@@ -670,6 +713,8 @@ srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_ne
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
   const Subject& su = p.subj[i];
   const Ptrs q = ptrs(c);
+  srm_status sa = ensure_a(c, i);
+  if (sa != SRM_OK) return sa;
   // Scratch: the E-phase partial buffer (free between iterations), used in
   // column chunks of [nsplit][KP][chunk] floats.
   const int64_t cap = (int64_t)(p.zpart_bytes / ((size_t)p.KP * 4));
@@ -697,6 +742,8 @@ srm_status srm_get_w(srm_ctx* c, int32_t i, float* dst) {
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
   const Ptrs q = ptrs(c);
+  srm_status sa = ensure_a(c, i);
+  if (sa != SRM_OK) return sa;
   WArgs wa{q.ah, q.al, c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP, dst,
            p.subj[i].row0, p.subj[i].v, p.k, p.prec};
   HIP_OR_FAIL(launch_get_w(c->stream, p.KP, wa));

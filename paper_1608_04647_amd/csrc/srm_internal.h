@@ -72,8 +72,9 @@ struct MArgs {
   void* ah;        // A records out (hi or FP32)
   void* al;        // A records out (lo)
   int64_t ldt;
-  int64_t total_rows;
-  int64_t ntiles;  // ceil(total_rows / 64)
+  int64_t row_begin;  // rows [row_begin, row_end), multiples of 32
+  int64_t row_end;
+  int64_t ntiles;     // ceil((row_end - row_begin) / 64)
   int64_t tiles_per_wg;
 };
 
@@ -89,6 +90,18 @@ struct EArgs {
   int64_t ldt;
   int32_t npanel;
   int32_t want_gram;
+};
+
+struct FusedArgs {
+  const void* xh;
+  const void* xl;
+  const void* sh;              // S records (current)
+  const void* sl;
+  const Slice* slices;
+  const int32_t* range_slice;  // [nranges + 1]
+  float* zpart;                // [nslices][KP][ldt]
+  float* gpart;                // [nslices][KP][KP]
+  int64_t ldt;
 };
 
 struct RArgs {

@@ -76,6 +76,25 @@ __device__ __forceinline__ void split8(const float (&v)[8], uint4& hi,
                   l[4] | (l[5] << 16), l[6] | (l[7] << 16));
 }
 
+
+// Buffer loads: a wave-uniform descriptor (base, byte size) plus a 32-bit
+// per-lane offset and a scalar offset.  Keeps per-load 64-bit addresses out
+// of vector registers in the streaming loops.
+typedef __attribute__((ext_vector_type(4))) unsigned v4u;
+typedef __attribute__((ext_vector_type(2))) unsigned v2u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 bload8(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_uint2(v.x, v.y);
+}
+
 // Workgroup ids are dealt round-robin to the 8 XCDs; map them so that
 // consecutive logical ids share an XCD (and its L2).
 __device__ __forceinline__ int xcd_remap(int h, int G) {
@@ -184,8 +203,8 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
   int64_t te = tb0 + a.tiles_per_wg;
   if (te > a.ntiles) te = a.ntiles;
   for (int64_t tile = tb0 + wave; tile < te; tile += 4) {
-    const int64_t rowt = tile * 64;
-    const bool h1 = rowt + 32 < a.total_rows;  // second 32-row half valid
+    const int64_t rowt = a.row_begin + tile * 64;
+    const bool h1 = rowt + 32 < a.row_end;  // second 32-row half valid
     f32x4 acc[4][NB];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
@@ -193,22 +212,22 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
       for (int jb = 0; jb < NB; ++jb) acc[mb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     if constexpr (PREC == P_FP32) {
-      const float* X = (const float*)a.xh;
-      const float4* SR = (const float4*)a.sh;
-      const int64_t nstep = a.ldt / 16;
-      for (int64_t tb = 0; tb < nstep; ++tb) {
+      const float* X = (const float*)a.xh + rowt * a.ldt;  // uniform
+      const int ld = (int)a.ldt;
+      const int nstep = ld / 16;
+      for (int tb = 0; tb < nstep; ++tb) {
         float4 x4[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           if (mb < 2 || h1)
-            x4[mb] = *(const float4*)(X + (rowt + 16 * mb + n) * a.ldt +
-                                      16 * tb + 4 * g);
+            x4[mb] = *(const float4*)(X + (16 * mb + n) * ld + 16 * tb + 4 * g);
           else
             x4[mb] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        const float4* SR = (const float4*)a.sh + tb * NB * 64;
         float4 s4[NB];
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) s4[jb] = SR[(tb * NB + jb) * 64 + lane];
+        for (int jb = 0; jb < NB; ++jb) s4[jb] = SR[jb * 64 + lane];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           if (mb >= 2 && !h1) continue;
@@ -222,16 +241,17 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
         }
       }
     } else {
-      const uint16_t* XH = (const uint16_t*)a.xh;
-      const uint16_t* XL = (const uint16_t*)a.xl;
-      const uint4* SH = (const uint4*)a.sh;
-      const uint4* SL = (const uint4*)a.sl;
-      const int64_t nstep = a.ldt / 32;
-      for (int64_t tb = 0; tb < nstep; ++tb) {
+      const uint16_t* XH = (const uint16_t*)a.xh + rowt * a.ldt;  // uniform
+      const uint16_t* XL = (const uint16_t*)a.xl + rowt * a.ldt;
+      const int ld = (int)a.ldt;
+      const int nstep = ld / 32;
+      for (int tb = 0; tb < nstep; ++tb) {
+        const uint4* SH = (const uint4*)a.sh + tb * NB * 64;
+        const uint4* SL = (const uint4*)a.sl + tb * NB * 64;
         uint4 xh4[4], xl4[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
-          const int64_t o = (rowt + 16 * mb + n) * a.ldt + 32 * tb + 8 * g;
+          const int o = (16 * mb + n) * ld + 32 * tb + 8 * g;
           if (mb < 2 || h1) {
             xh4[mb] = *(const uint4*)(XH + o);
             if constexpr (PREC == P_BF16X2) xl4[mb] = *(const uint4*)(XL + o);
@@ -243,8 +263,8 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
         uint4 sh4[NB], sl4[NB];
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          sh4[jb] = SH[(tb * NB + jb) * 64 + lane];
-          sl4[jb] = SL[(tb * NB + jb) * 64 + lane];
+          sh4[jb] = SH[jb * 64 + lane];
+          sl4[jb] = SL[jb * 64 + lane];
         }
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
@@ -321,26 +341,28 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
     for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int nblk = sl.nrows / 32;
+    const int ld = (int)a.ldt;
     for (int blk = 0; blk < nblk; ++blk) {
       const int64_t row0 = sl.row0 + 32 * blk;
       const int64_t rb = row0 / 32;
+      const int64_t xbase = row0 * a.ldt + cbase;  // wave-uniform
       if constexpr (PREC == P_FP32) {
-        const float4* AR = (const float4*)a.ah;
+        const float4* AR = (const float4*)a.ah + rb * NB * 128;  // uniform
         float av[NB][8];
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          const int64_t rec = (rb * NB + jb) * 64 + lane;
+          const int rec = jb * 64 + lane;
           const float4 p0 = AR[rec * 2], p1 = AR[rec * 2 + 1];
           av[jb][0] = p0.x; av[jb][1] = p0.y; av[jb][2] = p0.z; av[jb][3] = p0.w;
           av[jb][4] = p1.x; av[jb][5] = p1.y; av[jb][6] = p1.z; av[jb][7] = p1.w;
         }
         if (do_z) {
-          const float* X = (const float*)a.xh;
+          const float* X = (const float*)a.xh + xbase;
           float4 xv[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const int64_t r = row0 + 4 * g + (e & 3) + 16 * (e >> 2);
-            xv[e] = *(const float4*)(X + r * a.ldt + cbase + 4 * n);
+            const int o = (4 * g + (e & 3) + 16 * (e >> 2)) * ld + 4 * n;
+            xv[e] = *(const float4*)(X + o);
           }
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -364,23 +386,21 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
                   gacc[p >> 2] = mfma_f32(av[j1][e], av[j2][e], gacc[p >> 2]);
         }
       } else {
-        const uint4* AH = (const uint4*)a.ah;
-        const uint4* AL = (const uint4*)a.al;
+        const uint4* AH = (const uint4*)a.ah + rb * NB * 64;  // uniform
+        const uint4* AL = (const uint4*)a.al + rb * NB * 64;
         uint4 ah[NB], al[NB];
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          const int64_t rec = (rb * NB + jb) * 64 + lane;
-          ah[jb] = AH[rec];
-          al[jb] = AL[rec];
+          ah[jb] = AH[jb * 64 + lane];
+          al[jb] = AL[jb * 64 + lane];
         }
         if (do_z) {
-          const uint16_t* XH = (const uint16_t*)a.xh;
-          const uint16_t* XL = (const uint16_t*)a.xl;
+          const uint16_t* XH = (const uint16_t*)a.xh + xbase;
+          const uint16_t* XL = (const uint16_t*)a.xl + xbase;
           uint2 xv[8], xw[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const int64_t r = row0 + 4 * g + (e & 3) + 16 * (e >> 2);
-            const int64_t o = r * a.ldt + cbase + 4 * n;
+            const int o = (4 * g + (e & 3) + 16 * (e >> 2)) * ld + 4 * n;
             xv[e] = *(const uint2*)(XH + o);
             if constexpr (PREC == P_BF16X2) xw[e] = *(const uint2*)(XL + o);
           }
@@ -434,13 +454,13 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
     }
     // Z tile: lane holds Z[16 jb + 4 g + i][cbase + 4 n + q].
     if (do_z) {
-      float* zp = a.zpart + (int64_t)s * KP * a.ldt;
+      float* zp = a.zpart + (int64_t)s * KP * a.ldt + cbase;  // uniform
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int j = 16 * jb + 4 * g + i;
-          *(float4*)(zp + j * a.ldt + cbase + 4 * n) =
+          *(float4*)(zp + j * ld + 4 * n) =
               make_float4(acc[jb][0][i], acc[jb][1][i], acc[jb][2][i],
                           acc[jb][3][i]);
         }
@@ -457,6 +477,219 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
             for (int i = 0; i < 4; ++i)
               gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p >> 2][i];
     }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// One-pass sweep (BF16 forms, K padding <= 64, ldt in {128, 256, 384, 512}):
+// Xhat is read from HBM once per iteration.  Workgroup = NW = ldt / 64 waves
+// with all of S (bf16 hi+lo records) resident in LDS for the whole launch.
+// Each slice is walked in chunks of CH = 16 NW rows:
+//   part 1: each wave forms a 16-row block of A = Xhat S^T (all of its
+//           features, or one half) over all TRs; its Xhat rows stream from
+//           HBM through an 8-deep register ring,
+//           S operands come from LDS; the bf16 hi+lo result is written into
+//           the chunk's A records in LDS;
+//   part 2: after one barrier, wave w adds A^T Xhat[:, 64 w .. 64 w + 63]
+//           over the chunk into its Z columns (the chunk's Xhat is re-read
+//           while cache resident) and its share of the Gram tiles A^T A.
+// Z_s and G_s per slice equal what the two-pass E-phase forms from
+// A = Xhat S^T; A itself never goes to HBM.
+// ---------------------------------------------------------------------------
+template <int KP, int PREC, int NW>
+__global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
+  static_assert(PREC != P_FP32, "one-pass sweep is for the BF16 forms");
+  static_assert(NW % 2 == 0, "chunks are whole 32-row A records");
+  constexpr bool X2 = PREC == P_BF16X2;
+  constexpr int NB = KP / 16;
+  constexpr int NPAIR = NB * (NB + 1) / 2;
+  constexpr int NG = (NPAIR + NW - 1) / NW;
+  constexpr int LDT = 64 * NW;
+  constexpr int NSTEP = LDT / 32;  // 32-TR MFMA steps
+  // Part 1 may split the features of a 16-row block over NJP waves (smaller
+  // chunks); one part per wave measured fastest.
+  constexpr int NJP = 1;
+  constexpr int CH = 16 * NW / NJP;
+  constexpr int NRB = CH / 32;     // A records (32-row blocks) per chunk
+  constexpr int NBP = NB / NJP;    // feature blocks per part-1 wave
+  constexpr int D = 8;             // Xhat prefetch depth in part 1
+  __shared__ uint4 SHs[NSTEP][NB][64];
+  __shared__ uint4 SLs[NSTEP][NB][64];
+  __shared__ uint2 ARH[NRB][NB][64][2];  // [.][.][lane][row half]
+  __shared__ uint2 ARL[NRB][NB][64][2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const uint16_t* XH = (const uint16_t*)a.xh;
+  const uint16_t* XL = (const uint16_t*)a.xl;
+  const int c0 = 64 * wave;
+
+  // S records (current posterior mean) -> LDS, once.
+  for (int r = threadIdx.x; r < NSTEP * NB * 64; r += NW * 64) {
+    (&SHs[0][0][0])[r] = ((const uint4*)a.sh)[r];
+    (&SLs[0][0][0])[r] = ((const uint4*)a.sl)[r];
+  }
+  __syncthreads();
+
+  const int sb = a.range_slice[blockIdx.x], se = a.range_slice[blockIdx.x + 1];
+  for (int s = sb; s < se; ++s) {
+    const Slice sc = a.slices[s];
+    f32x4 zacc[NB][4];
+    f32x4 gacc[NG];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zacc[jb][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cr = 0; cr < sc.nrows; cr += CH) {
+      const int nrow = min(CH, sc.nrows - cr);  // multiple of 32
+      const int64_t rc = sc.row0 + cr;
+      // ---- part 1: rows [16 rw, 16 rw + 16), feature blocks of part jp
+      const int rw = wave % (CH / 16), jp = wave / (CH / 16);
+      if (16 * rw < nrow) {
+        const uint32_t wbytes = 16u * LDT * 2u;
+        const auto RH = make_rsrc(XH + (rc + 16 * rw) * LDT, wbytes);
+        const auto RL = make_rsrc(XL + (rc + 16 * rw) * LDT, wbytes);
+        const int vx = (n * LDT + 8 * g) * 2;
+        f32x4 acc[NBP];
+#pragma unroll
+        for (int jb = 0; jb < NBP; ++jb) acc[jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        uint4 xh[D], xl[D];
+#pragma unroll
+        for (int st = 0; st < D && st < NSTEP; ++st) {
+          xh[st] = bload16(RH, vx, st * 64);
+          if constexpr (X2) xl[st] = bload16(RL, vx, st * 64);
+        }
+#pragma unroll
+        for (int tb0 = 0; tb0 < NSTEP; tb0 += D) {
+#pragma unroll
+          for (int st = 0; st < D && tb0 + st < NSTEP; ++st) {
+            const int tb = tb0 + st;
+            const uint4 xa = xh[st];
+            uint4 xb;
+            if constexpr (X2) xb = xl[st];
+            if (tb + D < NSTEP) {  // refill this ring slot
+              xh[st] = bload16(RH, vx, (tb + D) * 64);
+              if constexpr (X2) xl[st] = bload16(RL, vx, (tb + D) * 64);
+            }
+#pragma unroll
+            for (int jj = 0; jj < NBP; ++jj) {
+              const int jb = jp * NBP + jj;
+              const uint4 th = SHs[tb][jb][lane], tl = SLs[tb][jb][lane];
+              acc[jj] = mfma_bf16(xa, th, acc[jj]);
+              acc[jj] = mfma_bf16(xa, tl, acc[jj]);
+              if constexpr (X2) acc[jj] = mfma_bf16(xb, th, acc[jj]);
+            }
+          }
+        }
+        // lane holds A[16 rw + 4 g + i][16 jb + n]: half of an A record
+#pragma unroll
+        for (int jj = 0; jj < NBP; ++jj) {
+          const int jb = jp * NBP + jj;
+          uint32_t h[4], l[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            h[i] = f2bf(acc[jj][i]);
+            l[i] = f2bf(acc[jj][i] - bf2f(h[i]));
+          }
+          ARH[rw >> 1][jb][lane][rw & 1] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+          ARL[rw >> 1][jb][lane][rw & 1] = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+        }
+      }
+      __syncthreads();
+      // ---- part 2: Z[:, 64 w ..] += A^T Xhat, Gram tiles
+      {
+        const int nblk = nrow / 32;
+        const uint32_t cbytes = (uint32_t)nrow * LDT * 2u;
+        const auto RH = make_rsrc(XH + rc * LDT + c0, cbytes);
+        const auto RL = make_rsrc(XL + rc * LDT + c0, cbytes);
+        const int vx = (4 * g * LDT + 4 * n) * 2;
+        uint2 xv[2][8], xw[2][8];
+        auto load = [&](int b, int buf) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int so = (32 * b + (e & 3) + 16 * (e >> 2)) * LDT * 2;
+            xv[buf][e] = bload8(RH, vx, so);
+            if constexpr (X2) xw[buf][e] = bload8(RL, vx, so);
+          }
+        };
+        auto block = [&](int b, int buf) {
+          uint4 ah[NB], al[NB];
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb) {
+            const uint2 h0 = ARH[b][jb][lane][0], h1 = ARH[b][jb][lane][1];
+            const uint2 l0 = ARL[b][jb][lane][0], l1 = ARL[b][jb][lane][1];
+            ah[jb] = make_uint4(h0.x, h0.y, h1.x, h1.y);
+            al[jb] = make_uint4(l0.x, l0.y, l1.x, l1.y);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            uint4 bh, bl;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const uint32_t a0 = (q < 2) ? xv[buf][2 * d].x : xv[buf][2 * d].y;
+              const uint32_t a1 = (q < 2) ? xv[buf][2 * d + 1].x : xv[buf][2 * d + 1].y;
+              ((uint32_t*)&bh)[d] = (q & 1) ? ((a0 >> 16) | (a1 & 0xffff0000u))
+                                            : ((a0 & 0xffffu) | (a1 << 16));
+              if constexpr (X2) {
+                const uint32_t b0 = (q < 2) ? xw[buf][2 * d].x : xw[buf][2 * d].y;
+                const uint32_t b1 = (q < 2) ? xw[buf][2 * d + 1].x : xw[buf][2 * d + 1].y;
+                ((uint32_t*)&bl)[d] = (q & 1) ? ((b0 >> 16) | (b1 & 0xffff0000u))
+                                              : ((b0 & 0xffffu) | (b1 << 16));
+              }
+            }
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+              zacc[jb][q] = mfma_bf16(ah[jb], bh, zacc[jb][q]);
+              zacc[jb][q] = mfma_bf16(al[jb], bh, zacc[jb][q]);
+              if constexpr (X2) zacc[jb][q] = mfma_bf16(ah[jb], bl, zacc[jb][q]);
+            }
+          }
+          int p = 0;
+#pragma unroll
+          for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+            for (int j2 = j1; j2 < NB; ++j2, ++p)
+              if ((p % NW) == wave) {
+                gacc[p / NW] = mfma_bf16(ah[j1], ah[j2], gacc[p / NW]);
+                gacc[p / NW] = mfma_bf16(ah[j1], al[j2], gacc[p / NW]);
+                gacc[p / NW] = mfma_bf16(al[j1], ah[j2], gacc[p / NW]);
+                gacc[p / NW] = mfma_bf16(al[j1], al[j2], gacc[p / NW]);
+              }
+        };
+        load(0, 0);
+        for (int b = 0; b < nblk; b += 2) {
+          if (b + 1 < nblk) load(b + 1, 1);
+          block(b, 0);
+          if (b + 1 >= nblk) break;
+          if (b + 2 < nblk) load(b + 2, 0);
+          block(b + 1, 1);
+        }
+      }
+      __syncthreads();
+    }
+    // Z tile: lane holds Z[16 jb + 4 g + i][c0 + 4 n + q].
+    float* zp = a.zpart + (int64_t)s * KP * LDT + c0;  // uniform
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = 16 * jb + 4 * g + i;
+        *(float4*)(zp + j * LDT + 4 * n) =
+            make_float4(zacc[jb][0][i], zacc[jb][1][i], zacc[jb][2][i], zacc[jb][3][i]);
+      }
+    float* gp = a.gpart + (int64_t)s * KP * KP;
+    int p = 0;
+#pragma unroll
+    for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+      for (int j2 = j1; j2 < NB; ++j2, ++p)
+        if ((p % NW) == wave)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p / NW][i];
   }
 }
 
@@ -1044,6 +1277,29 @@ hipError_t launch_transform(hipStream_t st, int kp, int nsplit, const TArgs& a,
   SRM_KP_SWITCH(kp,
       hipLaunchKernelGGL((k_transform_part<KP>), dim3(ncol, nsplit), dim3(256), 0, st, a);
       hipLaunchKernelGGL((k_transform_fin<KP>), dim3(ncol), dim3(256), 0, st, f));
+  return hipGetLastError();
+}
+
+bool fused_supported(int kp, int prec, int64_t ldt) {
+  return prec != P_FP32 && kp <= 64 && ldt <= 512 && ldt % 128 == 0;
+}
+hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
+                        const FusedArgs& a) {
+  const int nw = (int)(ldt / 64);
+#define SRM_FUSED_NW(NWV)                                                       \
+  case NWV:                                                                     \
+    SRM_KP_SWITCH(kp, if constexpr (KP <= 64) {                                 \
+      if (prec == P_BF16)                                                       \
+        hipLaunchKernelGGL((k_fused<KP, P_BF16, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
+      else                                                                      \
+        hipLaunchKernelGGL((k_fused<KP, P_BF16X2, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
+    });                                                                         \
+    break;
+  switch (nw) {
+    SRM_FUSED_NW(2) SRM_FUSED_NW(4) SRM_FUSED_NW(6) SRM_FUSED_NW(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef SRM_FUSED_NW
   return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ class SRM:
         _check(_lib.srm_fit(self._ctx, int(n_iter), ll.ctypes.data_as(_DP)))
         return ll[:n_iter]
 
-    PHASES = ("mphase", "ephase", "polar", "ereduce", "posterior")
+    PHASES = ("mphase", "ephase", "polar", "ereduce", "posterior", "fused")
 
     def profile(self, n_iter: int) -> dict:
         """Milliseconds per kernel phase summed over n_iter iterations, from HIP

@@ -185,3 +185,27 @@ def test_getters_before_first_iteration():
         g.W(0)
     assert ei.value.status == srm.SRM_E_STATE
     assert len(g.loglik()) == 1
+
+
+@pytest.mark.parametrize("case", ["tiny", "slices", "ragged"])
+def test_fused_and_two_pass_sweeps_agree(case):
+    """The one-pass sweep (A never stored) and the two-pass sweep (A = Xhat S^T
+    written, then A^T Xhat) are the same EM; both meet the BF16 bar against the
+    oracle and agree with each other to rounding."""
+    srm = _srm()
+    w = CASES[case]
+    d = synth.generate(w, seed=3)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"], final_loglik=True)
+    fits = {}
+    for name, flags in (("fused", 0), ("two_pass", srm.SRM_TWO_PASS)):
+        g = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+        g.fit(w.n_iter)
+        e = compare(g, ora, w.n_subjects)
+        _say(f"[errors] {case}/{name}: " + ", ".join(
+            f"{k}={v:.2e}" for k, v in e.items() if k != "ll_gpu"))
+        assert e["S"] <= 1e-3 and e["W"] <= 1e-3 and e["rho2"] <= 1e-3
+        fits[name] = g
+    a, b = fits["fused"], fits["two_pass"]
+    for i in range(w.n_subjects):
+        assert proj_err(a.W(i).cpu().numpy(), b.W(i).cpu().numpy()) <= 1e-4
+    assert np.allclose(a.rho2(), b.rho2(), rtol=1e-4)
