@@ -41,7 +41,7 @@ struct Scalars {
   int32_t ll_count;     // log-likelihoods written so far
   int32_t status;       // 0 ok, else an srm_status code raised on the device
   int32_t nonfinite;    // set by the conversion kernel
-  int32_t pad_;
+  int32_t polar_warm;   // stored eigenvectors are a valid warm start
 };
 
 constexpr int kLLCapacity = 1 << 16;
@@ -172,7 +172,8 @@ struct QArgs {
   const double* c;
   double* rho2;
   double* P64;
-  double* work;  // [N][2][KP][KP+1] global scratch (KP > 96)
+  double* work;   // [N][2][KP][KP+1] global scratch (KP > 96)
+  double* vprev;  // [N][KP][KP] eigenvectors of the previous iteration
   Scalars* sc;
   int32_t k;
   int64_t t;

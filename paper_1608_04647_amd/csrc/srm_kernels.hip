@@ -984,33 +984,69 @@ __global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
 template <int KP>
 __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
+  // Warm start keeps G, V and a product buffer in LDS (K padding <= 80);
+  // larger K keeps G and V in LDS (<= 96) or in global scratch, cold start.
+  constexpr bool WARM = KP <= 80;
   constexpr bool IN_LDS = KP <= 96;
+  constexpr int NBUF = WARM ? 3 : 2;
   constexpr int MAXP = (KP + 1) / 2;
-  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
+  __shared__ double lds[IN_LDS ? NBUF * KP * LD : 1];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
-  __shared__ double red[4];
   const int i = blockIdx.x, tid = threadIdx.x, k = a.k;
   double* G = IN_LDS ? lds : a.work + (int64_t)i * 2 * KP * LD;
   double* V = G + KP * LD;
   const Subject su = a.subj[i];
+  const int m = (k + 1) & ~1;  // even player count; index k (if k odd) is a dummy
+  const int npair = m / 2;
 
-  // G_i from the slices' upper 16x16 tiles, mirrored.
-  for (int idx = tid; idx < k * k; idx += 256) {
-    const int p = idx / k, q = idx % k;
-    const int r = p <= q ? p : q, cc = p <= q ? q : p;
+  // G_i from the slices' upper 16x16 tiles, mirrored; dummy row/col zero.
+  for (int idx = tid; idx < m * m; idx += 256) {
+    const int p = idx / m, q = idx % m;
     double s = 0.0;
-    for (int sl = su.s_beg; sl < su.s_end; ++sl)
-      s += (double)a.gpart[(int64_t)sl * KP * KP + r * KP + cc];
+    if (p < k && q < k) {
+      const int r = p <= q ? p : q, cc = p <= q ? q : p;
+      for (int sl = su.s_beg; sl < su.s_end; ++sl)
+        s += (double)a.gpart[(int64_t)sl * KP * KP + r * KP + cc];
+    }
     G[p * LD + q] = s;
-    V[p * LD + q] = (p == q) ? 1.0 : 0.0;
+  }
+  const bool warm = WARM && a.sc->polar_warm != 0;
+  if constexpr (WARM) {
+    double* T = V + KP * LD;
+    const double* Vp = a.vprev + (int64_t)i * KP * KP;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int p = idx / m, q = idx % m;
+      V[p * LD + q] = warm ? Vp[p * KP + q] : (p == q && p < k ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (warm) {  // G <- V^T G V, then rotate further from V
+      for (int idx = tid; idx < k * k; idx += 256) {
+        const int p = idx / k, q = idx % k;
+        double s = 0.0;
+        for (int r = 0; r < k; ++r) s += G[p * LD + r] * V[r * LD + q];
+        T[p * LD + q] = s;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < k * k; idx += 256) {
+        const int p = idx / k, q = idx % k;
+        double s = 0.0;
+        for (int r = 0; r < k; ++r) s += V[r * LD + p] * T[r * LD + q];
+        G[p * LD + q] = s;
+      }
+    }
+  } else {
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int p = idx / m, q = idx % m;
+      V[p * LD + q] = (p == q && p < k) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
 
-  // Cyclic Jacobi, round-robin (circle) ordering of the k(k-1)/2 pairs.
-  const int m = (k + 1) & ~1;  // even player count (index k is a dummy)
-  const int npair = m / 2;
+  // Cyclic Jacobi, round-robin (circle) ordering.  Each round's rotations
+  // act on disjoint index pairs, so G <- J^T G J splits into independent
+  // 2x2 blocks B_xy <- J_x^T B_xy J_y, and V <- V J into row pairs.
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -1041,31 +1077,26 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
         cs_[tid] = c;
         sn_[tid] = s;
         pp_[tid] = p;
-        qq_[tid] = q < k ? q : -1;
+        qq_[tid] = q;
       }
       __syncthreads();
-      // rows p, q of G <- J^T G
-      for (int idx = tid; idx < npair * k; idx += 256) {
-        const int x = idx / k, j = idx % k;
-        const int q = qq_[x];
-        if (q < 0) continue;
-        const int p = pp_[x];
-        const double c = cs_[x], s = sn_[x];
-        const double gp = G[p * LD + j], gq = G[q * LD + j];
-        G[p * LD + j] = c * gp - s * gq;
-        G[q * LD + j] = s * gp + c * gq;
+      for (int idx = tid; idx < npair * npair; idx += 256) {
+        const int x = idx / npair, y = idx % npair;
+        const int p = pp_[x], q = qq_[x], r = pp_[y], t = qq_[y];
+        const double cx = cs_[x], sx = sn_[x], cy = cs_[y], sy = sn_[y];
+        const double b00 = G[p * LD + r], b01 = G[p * LD + t];
+        const double b10 = G[q * LD + r], b11 = G[q * LD + t];
+        const double m00 = cx * b00 - sx * b10, m01 = cx * b01 - sx * b11;
+        const double m10 = sx * b00 + cx * b10, m11 = sx * b01 + cx * b11;
+        G[p * LD + r] = cy * m00 - sy * m01;
+        G[p * LD + t] = sy * m00 + cy * m01;
+        G[q * LD + r] = cy * m10 - sy * m11;
+        G[q * LD + t] = sy * m10 + cy * m11;
       }
-      __syncthreads();
-      // columns p, q of G and V <- (.) J
-      for (int idx = tid; idx < npair * k; idx += 256) {
-        const int x = idx / k, j = idx % k;
-        const int q = qq_[x];
-        if (q < 0) continue;
-        const int p = pp_[x];
+      for (int idx = tid; idx < npair * m; idx += 256) {
+        const int x = idx / m, j = idx % m;
+        const int p = pp_[x], q = qq_[x];
         const double c = cs_[x], s = sn_[x];
-        const double hp = G[j * LD + p], hq = G[j * LD + q];
-        G[j * LD + p] = c * hp - s * hq;
-        G[j * LD + q] = s * hp + c * hq;
         const double vp = V[j * LD + p], vq = V[j * LD + q];
         V[j * LD + p] = c * vp - s * vq;
         V[j * LD + q] = s * vp + c * vq;
@@ -1085,7 +1116,6 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   }
   const bool rank_ok = lmin > 1e-13 * lmax && lmax > 0.0;
   for (int j = 0; j < k; ++j) ssq += sqrt(fmax(G[j * LD + j], 0.0));
-  __syncthreads();
   // P = V diag(lambda^-1/2) V^T  (written zero padded to KP x KP)
   double* P = a.P64 + (int64_t)i * KP * KP;
   for (int idx = tid; idx < KP * KP; idx += 256) {
@@ -1097,12 +1127,25 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
     }
     P[idx] = s;
   }
+  if constexpr (WARM) {
+    double* Vp = a.vprev + (int64_t)i * KP * KP;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int p = idx / m, q = idx % m;
+      Vp[p * KP + q] = V[p * LD + q];
+    }
+  }
   if (tid == 0) {
     const double t = (double)a.t;
     const double r = (a.c[i] - 2.0 * ssq + t * a.sc->tau_cur) / (t * su.v);
     a.rho2[i] = rank_ok ? r : 1.0;
     if (!rank_ok && a.sc->status == 0) a.sc->status = 4;  // SRM_E_RANK
   }
+}
+
+// Marks the stored eigenvectors as a valid warm start (after every subject's
+// polar step of an iteration).
+__global__ void k_polar_done(Scalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc->polar_warm = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1263,6 +1306,7 @@ hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
 }
 hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
   SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_polar<KP>), dim3(N), dim3(256), 0, st, a));
+  hipLaunchKernelGGL(k_polar_done, dim3(1), dim3(64), 0, st, a.sc);
   return hipGetLastError();
 }
 hipError_t launch_get_w(hipStream_t st, int kp, const WArgs& a) {
