@@ -33,6 +33,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1608_04647_amd", "csrc", "srm_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_<prec>_traffic.md), or None when absent or
+    taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("traffic:"):
+            for kv in line.split(":", 1)[1].split():
+                k_, v_ = kv.split("=")
+                vals[k_] = v_
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def algorithmic(w, v, prec):
     """Bytes and flops one EM iteration must move and compute (unpadded sizes).
 
@@ -140,6 +169,9 @@ def main():
     ap.add_argument("--cpu-subjects", type=int, default=8)
     ap.add_argument("--subjects", type=int, default=0,
                     help="development only: fewer subjects of the same shape")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="GB: also run one plain device copy of this size "
+                         "(calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -189,7 +221,8 @@ def main():
         roof = {"bound": "hbm", "achieved": alg["bytes"] / dur / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = committed_traffic(f"k_{dom}", w.name if not args.subjects else
+                                        f"{w.name}-{args.subjects}", hp)
     roof["kernel"] = f"k_{dom}"
     roof["kernel_ms"] = ph[dom]
 
@@ -214,6 +247,16 @@ def main():
         out[f"speedup_vs_{prec}"] = head["iters_per_s"] / r["iters_per_s"]
     if check is not None:
         out["error_vs_oracle"] = check
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * 1e9) // 4 * 4
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
+        del src, dst
+        log(f"[bench] copy probe: {nbytes} bytes read and written")
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, args.seed, min(args.cpu_subjects, w.n_subjects))
