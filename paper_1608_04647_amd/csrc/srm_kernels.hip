@@ -513,7 +513,7 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
   constexpr int CH = 16 * NW / NJP;
   constexpr int NRB = CH / 32;     // A records (32-row blocks) per chunk
   constexpr int NBP = NB / NJP;    // feature blocks per part-1 wave
-  constexpr int D = 8;             // Xhat prefetch depth in part 1
+  constexpr int D = 4;             // Xhat prefetch depth in part 1
   __shared__ uint4 SHs[NSTEP][NB][64];
   __shared__ uint4 SLs[NSTEP][NB][64];
   __shared__ uint2 ARH[NRB][NB][64][2];  // [.][.][lane][row half]
@@ -562,27 +562,39 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
           xh[st] = bload16(RH, vx, st * 64);
           if constexpr (X2) xl[st] = bload16(RL, vx, st * 64);
         }
+        // S operands are read from LDS one step ahead (double buffer) so
+        // their latency hides behind the previous step's products.
+        uint4 th[2][NBP], tl[2][NBP];
 #pragma unroll
-        for (int tb0 = 0; tb0 < NSTEP; tb0 += D) {
+        for (int jj = 0; jj < NBP; ++jj) {
+          th[0][jj] = SHs[0][jp * NBP + jj][lane];
+          tl[0][jj] = SLs[0][jp * NBP + jj][lane];
+        }
 #pragma unroll
-          for (int st = 0; st < D && tb0 + st < NSTEP; ++st) {
-            const int tb = tb0 + st;
-            const uint4 xa = xh[st];
-            uint4 xb;
-            if constexpr (X2) xb = xl[st];
-            if (tb + D < NSTEP) {  // refill this ring slot
-              xh[st] = bload16(RH, vx, (tb + D) * 64);
-              if constexpr (X2) xl[st] = bload16(RL, vx, (tb + D) * 64);
-            }
+        for (int tb = 0; tb < NSTEP; ++tb) {
+          const int st = tb % D, sb2 = tb & 1;
+          if (tb + 1 < NSTEP) {
 #pragma unroll
             for (int jj = 0; jj < NBP; ++jj) {
-              const int jb = jp * NBP + jj;
-              const uint4 th = SHs[tb][jb][lane], tl = SLs[tb][jb][lane];
-              acc[jj] = mfma_bf16(xa, th, acc[jj]);
-              acc[jj] = mfma_bf16(xa, tl, acc[jj]);
-              if constexpr (X2) acc[jj] = mfma_bf16(xb, th, acc[jj]);
+              th[sb2 ^ 1][jj] = SHs[tb + 1][jp * NBP + jj][lane];
+              tl[sb2 ^ 1][jj] = SLs[tb + 1][jp * NBP + jj][lane];
             }
           }
+          const uint4 xa = xh[st];
+          uint4 xb;
+          if constexpr (X2) xb = xl[st];
+          if (tb + D < NSTEP) {  // refill this ring slot
+            xh[st] = bload16(RH, vx, (tb + D) * 64);
+            if constexpr (X2) xl[st] = bload16(RL, vx, (tb + D) * 64);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int jj = 0; jj < NBP; ++jj) {
+            acc[jj] = mfma_bf16(xa, th[sb2][jj], acc[jj]);
+            acc[jj] = mfma_bf16(xa, tl[sb2][jj], acc[jj]);
+            if constexpr (X2) acc[jj] = mfma_bf16(xb, th[sb2][jj], acc[jj]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
         // lane holds A[16 rw + 4 g + i][16 jb + n]: half of an A record
 #pragma unroll
