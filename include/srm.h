@@ -75,9 +75,12 @@ enum {
   SRM_NO_GRAPH = 1u,    /* launch each iteration's kernels directly instead of
                            replaying one captured hipGraph                     */
   SRM_NO_W0_CHECK = 2u, /* skip the host check that W0_i^T W0_i = I            */
-  SRM_TWO_PASS = 4u     /* use the two-pass sweep (A = Xhat S^T to HBM, then
+  SRM_TWO_PASS = 4u,    /* use the two-pass sweep (A = Xhat S^T to HBM, then
                            A^T Xhat) even where the fused one-pass sweep applies
                            (BF16 forms with k <= 64 and t <= 512)              */
+  SRM_X_HOST = 8u       /* srm_init's X[i] are host pointers: each subject is
+                           uploaded through a staging area in the workspace and
+                           converted there (no full FP32 copy on the device)  */
 };
 
 typedef struct {
@@ -99,8 +102,9 @@ srm_status srm_workspace_size(const srm_desc *desc, size_t *bytes);
  * store Xhat_i in desc->prec inside the workspace, compute c_i = ||Xhat_i||^2
  * from the stored values, set W_i = W0_i, rho_i^2 = 1, Sigma_s = I, and run
  * the first E-step (its log-likelihood is the first one srm_fit reports).
- *   X:  host array of N device pointers; X[i] is v_i x t float32, row stride t.
- *       Read during the call only (the caller keeps ownership).
+ *   X:  host array of N device pointers (host pointers with SRM_X_HOST);
+ *       X[i] is v_i x t float32, row stride t.  Read during the call only
+ *       (the caller keeps ownership).
  *   W0: host array of N host pointers; W0[i] is v_i x k float64 with
  *       orthonormal columns (checked: max|W0^T W0 - I| <= 1e-8 unless
  *       SRM_NO_W0_CHECK).  Read during the call only.

@@ -86,7 +86,8 @@ struct Plan {
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
          o_prepwork = 0, o_polwork = 0, o_vprev = 0, o_sc = 0, o_ll = 0, o_subj = 0,
-         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0;
+         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0;
+  size_t stage_bytes = 0;
   size_t total = 0;
   size_t arec_bytes = 0, srec_bytes = 0, zpart_bytes = 0;
 };
@@ -215,6 +216,12 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_srow0 = take(sizeof(int64_t) * p.N);
   p.o_sv = take(sizeof(int32_t) * p.N);
   p.o_xptr = take(sizeof(void*) * p.N);
+  if (d->flags & SRM_X_HOST) {  // staging for one subject's FP32 rows at a time
+    int64_t vmax = 0;
+    for (int i = 0; i < p.N; ++i) vmax = std::max<int64_t>(vmax, d->v[i]);
+    p.stage_bytes = (size_t)vmax * p.t * sizeof(float);
+    p.o_stage = take(p.stage_bytes);
+  }
   p.total = off;
   return SRM_OK;
 }
@@ -604,7 +611,7 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
       up(P.o_rs, P.range_slice.data(), sizeof(int32_t) * (P.nranges + 1)) != hipSuccess ||
       up(P.o_srow0, srow0.data(), sizeof(int64_t) * P.N) != hipSuccess ||
       up(P.o_sv, sv.data(), sizeof(int32_t) * P.N) != hipSuccess ||
-      up(P.o_xptr, X, sizeof(void*) * P.N) != hipSuccess ||
+      ((desc->flags & SRM_X_HOST) == 0 && up(P.o_xptr, X, sizeof(void*) * P.N) != hipSuccess) ||
       up(P.o_sc, &sc, sizeof sc) != hipSuccess ||
       up(P.o_rho2, ones.data(), sizeof(double) * P.N) != hipSuccess ||
       up(P.o_sigcur, eyeKP.data(), eyeKP.size() * 8) != hipSuccess ||
@@ -615,11 +622,30 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
 
   const Ptrs q = ptrs(c);
   ConvertArgs ca{c->at<const float* const>(P.o_xptr), c->at<int64_t>(P.o_srow0),
-                 c->at<int32_t>(P.o_sv), P.N, P.t, P.ldt, P.total_rows, q.xh, q.xl,
-                 c->at<double>(P.o_mu), c->at<double>(P.o_rowc), c->at<Scalars>(P.o_sc),
-                 P.prec};
-  if (launch_convert(c->stream, (int)((P.total_rows + 3) / 4), ca) != hipSuccess ||
-      launch_rowsum(c->stream, P.N, c->at<double>(P.o_rowc), c->at<Subject>(P.o_subj),
+                 c->at<int32_t>(P.o_sv), P.N, P.t, P.ldt, 0, P.total_rows, nullptr, -1,
+                 q.xh, q.xl, c->at<double>(P.o_mu), c->at<double>(P.o_rowc),
+                 c->at<Scalars>(P.o_sc), P.prec};
+  if (desc->flags & SRM_X_HOST) {
+    // Streamed ingestion: each subject's FP32 rows pass through one staging
+    // buffer in the workspace, then are demeaned and converted in place.
+    float* stage = c->at<float>(P.o_stage);
+    for (int i = 0; i < P.N; ++i) {
+      const Subject& su = P.subj[i];
+      if (hipMemcpyAsync(stage, X[i], (size_t)su.v * P.t * sizeof(float),
+                         hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return bail(fail(SRM_E_HIP, "upload of X[%d] failed", i));
+      ConvertArgs ci = ca;
+      ci.row_begin = su.row0;
+      ci.row_end = su.row0 + su.vp;
+      ci.stage = stage;
+      ci.stage_subj = i;
+      if (launch_convert(c->stream, (su.vp + 3) / 4, ci) != hipSuccess)
+        return bail(fail(SRM_E_HIP, "conversion launch failed"));
+    }
+  } else if (launch_convert(c->stream, (int)((P.total_rows + 3) / 4), ca) != hipSuccess) {
+    return bail(fail(SRM_E_HIP, "conversion launch failed"));
+  }
+  if (launch_rowsum(c->stream, P.N, c->at<double>(P.o_rowc), c->at<Subject>(P.o_subj),
                     c->at<double>(P.o_c)) != hipSuccess)
     return bail(fail(SRM_E_HIP, "conversion launch failed"));
   Scalars chk{};

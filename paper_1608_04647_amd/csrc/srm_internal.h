@@ -55,7 +55,11 @@ struct ConvertArgs {
   const int64_t* subj_row0;  // [N] first global row of each subject
   const int32_t* subj_v;     // [N]
   int32_t N;
-  int64_t t, ldt, total_rows;
+  int64_t t, ldt;
+  int64_t row_begin;         // rows [row_begin, row_end) are converted
+  int64_t row_end;
+  const float* stage;        // if set: subject stage_subj's rows come from here
+  int32_t stage_subj;
   void* xh;
   void* xl;
   double* mu;

@@ -128,8 +128,8 @@ __device__ double block_sum256(double v, double* red /* >= 4 */) {
 
 __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= a.total_rows) return;
+  const int64_t r = a.row_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= a.row_end) return;
   int lo = 0, hi = a.N - 1;  // last subject with row0 <= r
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -137,7 +137,8 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   }
   const int64_t lr = r - a.subj_row0[lo];
   const bool real = lr < a.subj_v[lo];
-  const float* src = real ? a.X[lo] + lr * a.t : nullptr;
+  const float* base = (a.stage && lo == a.stage_subj) ? a.stage : a.X[lo];
+  const float* src = real ? base + lr * a.t : nullptr;
   double s = 0.0;
   bool bad = false;
   if (real) {

@@ -28,7 +28,7 @@ SRM_OK, SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_HIP, SRM_E_RANK, SRM_E_NOTPD, \
 STATUS_NAMES = {0: "SRM_OK", 1: "SRM_E_ARG", 2: "SRM_E_WORKSPACE", 3: "SRM_E_HIP",
                 4: "SRM_E_RANK", 5: "SRM_E_NOTPD", 6: "SRM_E_NONFINITE", 7: "SRM_E_STATE"}
 PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2}
-SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS = 1, 2, 4
+SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST = 1, 2, 4, 8
 
 
 class SrmDesc(ctypes.Structure):
@@ -108,23 +108,30 @@ class SRM:
     """One SRM fit on the current HIP device.
 
     X: list of N float32 arrays (v_i x t): torch CUDA tensors are used in
-    place, anything else is uploaded.  W0: list of N float64 host arrays
-    (v_i x k, orthonormal columns); None draws random orthonormal maps."""
+    place, anything else is uploaded (or, with stream_from_host, streamed
+    through the library's staging area one subject at a time).  W0: list of
+    N float64 host arrays (v_i x k, orthonormal columns); None draws random
+    orthonormal maps."""
 
     def __init__(self, X, k: int, prec: str = "fp32", W0=None, flags: int = 0,
-                 seed: int = 0):
+                 seed: int = 0, stream_from_host: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise SRMError(SRM_E_HIP, "no HIP device visible")
         self._torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
         xs = []
-        for x in X:
-            if isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 \
-                    and x.is_contiguous():
-                xs.append(x)
-            else:
-                xs.append(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to(dev))
+        if stream_from_host:
+            flags |= SRM_X_HOST
+            for x in X:
+                xs.append(np.ascontiguousarray(x, dtype=np.float32))
+        else:
+            for x in X:
+                if isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 \
+                        and x.is_contiguous():
+                    xs.append(x)
+                else:
+                    xs.append(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to(dev))
         self.N = len(xs)
         self.v = [int(x.shape[0]) for x in xs]
         self.t = int(xs[0].shape[1])
@@ -138,7 +145,8 @@ class SRM:
         _check(_lib.srm_workspace_size(ctypes.byref(self._desc), ctypes.byref(n)))
         self.workspace_bytes = int(n.value)
         self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
-        xptr = (_P * self.N)(*[x.data_ptr() for x in xs])
+        xptr = (_P * self.N)(*[(x.ctypes.data if stream_from_host else x.data_ptr())
+                               for x in xs])
         wptr = (_P * self.N)(*[w.ctypes.data for w in w0])
         torch.cuda.synchronize()
         ctx = _P()

@@ -127,10 +127,11 @@ def subject(w: Workload, g: Globals, i: int, seed: int = 0,
     Wp = random_orthonormal(rng, vi, w.k)
     e = rng.standard_normal((vi, w.t), dtype=np.float32)
     if w.ar_phi != 0.0:
-        phi = np.float32(w.ar_phi)
-        c = np.float32(np.sqrt(1.0 - w.ar_phi ** 2))
-        for tau in range(1, w.t):
-            e[:, tau] = phi * e[:, tau - 1] + c * e[:, tau]
+        # e_0 = z_0, e_tau = phi e_(tau-1) + sqrt(1 - phi^2) z_tau (stationary
+        # unit variance), as one IIR filter along each voxel's time series.
+        from scipy.signal import lfilter
+        e[:, 1:] *= np.float32(np.sqrt(1.0 - w.ar_phi ** 2))
+        e = lfilter([1.0], [1.0, -w.ar_phi], e, axis=1).astype(np.float32, copy=False)
     X = Wp.astype(np.float32) @ g.S.astype(np.float32)
     X += np.float32(g.rho[i]) * e
     return (X, Wp) if want_w else X

@@ -86,3 +86,62 @@ def test_batch1024_full_size_sampled_m_step_and_properties():
              f"orth {orth:.2e}")
         assert ep <= 1e-3 and er <= 1e-3 and orth <= 1e-4
     g.close()
+
+
+def _sampled_m_step(g, w, gl, subjects, seed=0, prec=None):
+    S = g.S().cpu().numpy().astype(np.float64)
+    sig = g.sigma_s()
+    tau = float(np.trace(sig))
+    rho = g.rho2()
+    out = []
+    for i in subjects:
+        Xi = synth.subject(w, gl, i, seed=seed)
+        _, xh, c = oracle.demean(Xi)
+        Wo, r = oracle.m_step_subject(xh, c, S, tau)
+        Wg = g.W(i).cpu().numpy().astype(np.float64)
+        out.append((proj_err(Wo, Wg), abs(rho[i] / r - 1),
+                    float(np.abs(Wg.T @ Wg - np.eye(w.k)).max())))
+        _say(f"[errors] {w.name}/{prec} subject {i}: projector {out[-1][0]:.2e}, "
+             f"rho2 {out[-1][1]:.2e}, orth {out[-1][2]:.2e}")
+    return out
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,bar", [("fp32", 1e-4), ("bf16x2", 1e-3), ("bf16", 2e-2)])
+def test_precision40_full_size_sampled(prec, bar):
+    """40 subjects x 10k-100k voxels x 2000 TRs, k = 100 (K padding 112, the
+    two-pass sweep and the k x k steps outside LDS).  Plain BF16 is held to
+    its quantisation floor (the oracle sees the original data)."""
+    import torch
+    srm = _srm()
+    w = synth.WORKLOADS["precision40"]
+    X, W0, gl = synth.to_device(w, seed=0)
+    g = srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK)
+    del X
+    torch.cuda.empty_cache()
+    g.fit(3)
+    ll = g.loglik()
+    assert np.all(np.diff(ll) >= -1e-9 * np.abs(ll[:-1])), ll
+    for ep, er, orth in _sampled_m_step(g, w, gl, (0, 39), prec=prec):
+        assert ep <= bar and er <= bar and orth <= 1e-4
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_highres_subject_shape_streamed_from_host():
+    """The high-resolution subjects (400k-600k voxels x 1200 TRs, k = 100,
+    AR(1) noise) through streamed ingestion; 8 of the 64 subjects keep host
+    memory modest, the per-subject shapes are the workload's own."""
+    srm = _srm()
+    w = synth.WORKLOADS["highres64"]
+    sub = list(range(8))
+    d = synth.generate(w, seed=0, subjects=sub, threads=8)
+    g = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], stream_from_host=True,
+                flags=srm.SRM_NO_W0_CHECK)
+    g.fit(3)
+    ll = g.loglik()
+    assert np.all(np.diff(ll) >= -1e-9 * np.abs(ll[:-1])), ll
+    w8 = w.scaled(n_subjects=8)
+    for ep, er, orth in _sampled_m_step(g, w8, d["globals"], (0, 7), prec="bf16x2"):
+        assert ep <= 1e-3 and er <= 1e-3 and orth <= 1e-4
+    g.close()
