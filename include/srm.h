@@ -78,9 +78,15 @@ enum {
   SRM_TWO_PASS = 4u,    /* use the two-pass sweep (A = Xhat S^T to HBM, then
                            A^T Xhat) even where the fused one-pass sweep applies
                            (BF16 forms with k <= 64 and t <= 512)              */
-  SRM_X_HOST = 8u       /* srm_init's X[i] are host pointers: each subject is
+  SRM_X_HOST = 8u,      /* srm_init's X[i] are host pointers: each subject is
                            uploaded through a staging area in the workspace and
                            converted there (no full FP32 copy on the device)  */
+  SRM_ZSCORE = 16u      /* standardise each voxel (the z-score preprocessing of
+                           the paper's implementation, Sec. IV-A): after the
+                           mean, divide by the population standard deviation
+                           over the t samples (1/t).  A constant voxel is only
+                           demeaned.  srm_transform and srm_map apply the same
+                           per-voxel scale.                                    */
 };
 
 typedef struct {
@@ -159,6 +165,16 @@ srm_status srm_profile(srm_ctx *ctx, int32_t n_iter, double *ms);
 srm_status srm_transform(srm_ctx *ctx, int32_t i, const float *X_new,
                          int64_t t_new, float *S_out);
 
+/* Map new samples of subject i into subject j's voxel space through the
+ * shared space (Sec. II-A): Y_out = W_j W_i^T (X_new - mu_i 1^T), i.e. the
+ * projection of srm_transform followed by W_j.  The result is in subject j's
+ * demeaned space (add mu_j, from srm_get_mu, for its raw space).
+ *   X_new: device, v_i x t_new float32, row stride t_new.
+ *   Y_out: device, v_j x t_new float32, row stride t_new.
+ * Valid after at least one iteration (SRM_E_STATE otherwise).  Enqueues only. */
+srm_status srm_map(srm_ctx *ctx, int32_t i, int32_t j, const float *X_new,
+                   int64_t t_new, float *Y_out);
+
 /* Results of the last completed iteration (SRM_E_STATE before the first).
  *  srm_get_w:      device dst, v_i x k float32: W_i (orthonormal columns).
  *  srm_get_s:      device dst, k x t float32: the shared response E[S] of the
@@ -166,6 +182,9 @@ srm_status srm_transform(srm_ctx *ctx, int32_t i, const float *X_new,
  *  srm_get_rho2:   host dst [N] float64.
  *  srm_get_sigma_s:host dst k x k float64.
  *  srm_get_mu:     device dst, v_i float64: subject i's voxel means.
+ *  srm_get_scale:  device dst, v_i float64: the per-voxel factor applied after
+ *                  demeaning (1/std with SRM_ZSCORE, else 1).  Valid from
+ *                  srm_init on, like srm_get_mu.
  *  srm_get_loglik: host dst [capacity] float64, all log-likelihoods computed so
  *                  far (n_iter + 1 after n_iter iterations: the last one is the
  *                  log-likelihood of the final parameters); *count receives
@@ -176,8 +195,25 @@ srm_status srm_get_s(srm_ctx *ctx, float *dst);
 srm_status srm_get_rho2(srm_ctx *ctx, double *dst);
 srm_status srm_get_sigma_s(srm_ctx *ctx, double *dst);
 srm_status srm_get_mu(srm_ctx *ctx, int32_t i, double *dst);
+srm_status srm_get_scale(srm_ctx *ctx, int32_t i, double *dst);
 srm_status srm_get_loglik(srm_ctx *ctx, double *dst, int32_t capacity,
                           int32_t *count);
+
+/* Checkpoint and resume.  The state between iterations is the posterior of
+ * the last E-step (S, Sigma_s, tr Sigma_s, the k x k matrices M), the
+ * per-subject rho_i^2 and polar factors P_i with their eigenvectors, the
+ * log-likelihood history and the iteration count (Algorithm 1 carries exactly
+ * these from one iteration to the next; the data enter through Xhat_i only).
+ *  srm_get_state: host blob; with blob == NULL, *bytes receives the size.
+ *                 Otherwise *bytes must hold at least that size.  SRM_E_STATE
+ *                 before the first iteration.  Synchronises the stream.
+ *  srm_set_state: host blob from srm_get_state of a context with the same
+ *                 descriptor (N, v, t, k, format, sweep) and the same data
+ *                 (checked through c_i = ||Xhat_i||_F^2, bitwise): SRM_E_ARG
+ *                 otherwise.  Continuing from a restored state gives results
+ *                 bitwise identical to an uninterrupted fit.  Synchronises. */
+srm_status srm_get_state(srm_ctx *ctx, void *blob, size_t *bytes);
+srm_status srm_set_state(srm_ctx *ctx, const void *blob, size_t bytes);
 
 /* Number of completed iterations. */
 srm_status srm_iterations(const srm_ctx *ctx, int32_t *n);

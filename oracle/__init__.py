@@ -5,6 +5,6 @@ import this package.  The device library never calls it and shares no code
 with it.
 """
 from .srm_oracle import (  # noqa: F401
-    OracleRankError, OracleNotPD, demean, posterior, loglik, polar_svd,
+    OracleRankError, OracleNotPD, demean, zscore, posterior, loglik, polar_svd,
     m_step_subject, em_fit, naive_estep, fit_gram, flop_model,
 )

@@ -32,6 +32,12 @@ Readings of the paper used here (the paper is silent, ambiguous or garbled):
       the inversion lemma (Eq. 7) and Eq. 8 -- see ``loglik``.
   R10 a rank-deficient A_i (lambda_min(A^T A) <= 1e-13 lambda_max) is an error.
   R11 inversions by Cholesky (Sec. II-C); a failure is an error.
+  R12 the data standardisation (z-score) named among the implementation's
+      native helpers (Sec. IV-A) is taken per voxel over the samples, with the
+      population standard deviation (1/t); a constant voxel (standard
+      deviation 0) is only demeaned.  For float32 input the FP64 mean of a
+      constant voxel is exact (its sum is an exact multiple), so "constant"
+      needs no tolerance.
 
 Pins (tests/test_oracle.py): naive V x V E-step (Eq. 2-3), the closed form
 Sigma_s (I - rho0 M) = M, orthonormality, polar = SVD, the trace identity,
@@ -75,6 +81,21 @@ def demean(X: np.ndarray):
     Xh = X - mu[:, None]
     c = float(np.sum(Xh * Xh))  # trace(A^T A) of Sec. IV-A
     return mu, Xh, c
+
+
+def zscore(X: np.ndarray):
+    """Per-voxel standardisation of Sec. IV-A (R12): (x - mu) / sd with sd the
+    population standard deviation over the samples.
+
+    Returns (mu [v], Z [v x t] float64, scale [v] = 1/sd, or 1 for a constant
+    voxel)."""
+    X = np.asarray(X, dtype=np.float64)
+    mu = X.mean(axis=1)
+    D = X - mu[:, None]
+    sd = np.sqrt(np.mean(D * D, axis=1))
+    keep = sd > 0
+    scale = np.where(keep, 1.0 / np.where(keep, sd, 1.0), 1.0)
+    return mu, D * scale[:, None], scale
 
 
 def posterior(Y: np.ndarray, rho2: np.ndarray, Sigma_s: np.ndarray):

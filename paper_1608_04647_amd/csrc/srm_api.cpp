@@ -32,6 +32,7 @@ hipError_t launch_polar(hipStream_t, int, int, const QArgs&);
 hipError_t launch_get_w(hipStream_t, int, const WArgs&);
 hipError_t launch_transform(hipStream_t, int, int, const TArgs&, const TFArgs&);
 hipError_t occupancy_mphase(int, int, int*);
+hipError_t launch_map(hipStream_t, int, const MapArgs&);
 bool fused_supported(int kp, int prec, int64_t ldt);
 hipError_t launch_fused(hipStream_t, int, int, int64_t, int, const FusedArgs&);
 hipError_t occupancy_ephase(int, int, int*);
@@ -81,7 +82,7 @@ struct Plan {
   std::vector<Slice> slices;
   std::vector<int32_t> range_slice;
   // workspace offsets (bytes)
-  size_t o_xh = 0, o_xl = 0, o_mu = 0, o_rowc = 0, o_c = 0, o_arec = 0,
+  size_t o_xh = 0, o_xl = 0, o_mu = 0, o_isd = 0, o_rowc = 0, o_c = 0, o_arec = 0,
          o_zpart = 0, o_gpart = 0, o_p64 = 0, o_rho2 = 0, o_ygrp = 0,
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
@@ -185,6 +186,7 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_xh = take(xplane);
   p.o_xl = p.prec == SRM_BF16X2 ? take(xplane) : p.o_xh;
   p.o_mu = take(sizeof(double) * p.total_rows);
+  p.o_isd = take(sizeof(double) * p.total_rows);
   p.o_rowc = take(sizeof(double) * p.total_rows);
   p.o_c = take(sizeof(double) * p.N);
   p.arec_bytes = (size_t)p.total_rows * p.KP * 4;  // FP32, or 2 bf16 planes
@@ -623,8 +625,9 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
   const Ptrs q = ptrs(c);
   ConvertArgs ca{c->at<const float* const>(P.o_xptr), c->at<int64_t>(P.o_srow0),
                  c->at<int32_t>(P.o_sv), P.N, P.t, P.ldt, 0, P.total_rows, nullptr, -1,
-                 q.xh, q.xl, c->at<double>(P.o_mu), c->at<double>(P.o_rowc),
-                 c->at<Scalars>(P.o_sc), P.prec};
+                 q.xh, q.xl, c->at<double>(P.o_mu), c->at<double>(P.o_isd),
+                 c->at<double>(P.o_rowc), c->at<Scalars>(P.o_sc), P.prec,
+                 (desc->flags & SRM_ZSCORE) ? 1 : 0};
   if (desc->flags & SRM_X_HOST) {
     // Streamed ingestion: each subject's FP32 rows pass through one staging
     // buffer in the workspace, then are demeaned and converted in place.
@@ -730,6 +733,32 @@ srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
   return read_scalars(c, &sc);
 }
 
+// S_out[:, 0:tn] = W_i^T (X[:, 0:tn] - mu_i 1^T), X with row stride ldx and
+// S_out with row stride ldo; column chunks through the E-phase partial buffer.
+// Subject i's A rows must be current (ensure_a).
+static srm_status transform_cols(srm_ctx* c, int32_t i, const float* X, int64_t ldx,
+                                 int64_t ncols, float* S_out, int64_t ldo) {
+  const Plan& p = c->p;
+  const Subject& su = p.subj[i];
+  const Ptrs q = ptrs(c);
+  const int64_t cap = (int64_t)(p.zpart_bytes / ((size_t)p.KP * 4));
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(
+      std::min<int64_t>(64, (su.v + 2047) / 2048), cap / 64));
+  const int64_t chunk = std::max<int64_t>(64, std::min<int64_t>(
+      round_up(ncols, 64), cap / nsplit / 64 * 64));
+  if (chunk * nsplit > cap) return fail(SRM_E_WORKSPACE, "transform scratch too small");
+  const int rps = (int)((su.v + nsplit - 1) / nsplit);
+  for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
+    const int64_t tn = std::min(chunk, ncols - c0);
+    TArgs ta{q.ah, q.al, c->at<double>(p.o_mu), c->at<double>(p.o_isd), X + c0, c->at<float>(p.o_zpart),
+             su.row0, tn, ldx, su.v, rps, p.prec};
+    TFArgs tf{c->at<float>(p.o_zpart), c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP,
+              S_out + c0, tn, ldo, nsplit, p.k};
+    HIP_OR_FAIL(launch_transform(c->stream, p.KP, nsplit, ta, tf));
+  }
+  return SRM_OK;
+}
+
 srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_new,
                          float* S_out) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");
@@ -738,26 +767,35 @@ srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_ne
   if (!X_new || !S_out) return fail(SRM_E_ARG, "NULL buffer");
   if (t_new < 1) return fail(SRM_E_ARG, "t_new must be >= 1");
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
-  const Subject& su = p.subj[i];
-  const Ptrs q = ptrs(c);
-  srm_status sa = ensure_a(c, i);
+  const srm_status sa = ensure_a(c, i);
   if (sa != SRM_OK) return sa;
-  // Scratch: the E-phase partial buffer (free between iterations), used in
-  // column chunks of [nsplit][KP][chunk] floats.
-  const int64_t cap = (int64_t)(p.zpart_bytes / ((size_t)p.KP * 4));
-  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(
-      std::min<int64_t>(64, (su.v + 2047) / 2048), cap / 64));
-  const int64_t chunk = std::max<int64_t>(64, std::min<int64_t>(
-      round_up(t_new, 64), cap / nsplit / 64 * 64));
-  if (chunk * nsplit > cap) return fail(SRM_E_WORKSPACE, "transform scratch too small");
-  const int rps = (int)((su.v + nsplit - 1) / nsplit);
-  for (int64_t c0 = 0; c0 < t_new; c0 += chunk) {
-    const int64_t tn = std::min(chunk, t_new - c0);
-    TArgs ta{q.ah, q.al, c->at<double>(p.o_mu), X_new + c0, c->at<float>(p.o_zpart),
-             su.row0, tn, t_new, su.v, rps, p.prec};
-    TFArgs tf{c->at<float>(p.o_zpart), c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP,
-              S_out + c0, tn, t_new, nsplit, p.k};
-    HIP_OR_FAIL(launch_transform(c->stream, p.KP, nsplit, ta, tf));
+  return transform_cols(c, i, X_new, t_new, t_new, S_out, t_new);
+}
+
+srm_status srm_map(srm_ctx* c, int32_t i, int32_t j, const float* X_new, int64_t t_new,
+                   float* Y_out) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  const Plan& p = c->p;
+  if (i < 0 || i >= p.N || j < 0 || j >= p.N) return fail(SRM_E_ARG, "subject out of range");
+  if (!X_new || !Y_out) return fail(SRM_E_ARG, "NULL buffer");
+  if (t_new < 1) return fail(SRM_E_ARG, "t_new must be >= 1");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  // S_new = W_i^T (X_new - mu_i) in column chunks held in the Y-group
+  // scratch (free between iterations), then Y = A_j (P_j S_new).
+  const size_t cap_cols = (size_t)p.ngrp * p.ldt * 8 / ((size_t)p.KP * 4) / 64 * 64;
+  if (cap_cols < 64) return fail(SRM_E_WORKSPACE, "map scratch too small");
+  float* sbuf = c->at<float>(p.o_ygrp);
+  srm_status sa = ensure_a(c, i);
+  if (sa == SRM_OK && j != i) sa = ensure_a(c, j);
+  if (sa != SRM_OK) return sa;
+  const Ptrs q = ptrs(c);
+  for (int64_t c0 = 0; c0 < t_new; c0 += (int64_t)cap_cols) {
+    const int64_t tn = std::min<int64_t>((int64_t)cap_cols, t_new - c0);
+    sa = transform_cols(c, i, X_new + c0, t_new, tn, sbuf, tn);
+    if (sa != SRM_OK) return sa;
+    MapArgs ma{q.ah, q.al, c->at<double>(p.o_p64) + (size_t)j * p.KP * p.KP, sbuf,
+               Y_out + c0, p.subj[j].row0, tn, tn, t_new, p.subj[j].v, p.k, p.prec};
+    HIP_OR_FAIL(launch_map(c->stream, p.KP, ma));
   }
   return SRM_OK;
 }
@@ -825,6 +863,152 @@ srm_status srm_get_mu(srm_ctx* c, int32_t i, double* dst) {
   HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_mu + sizeof(double) * c->p.subj[i].row0,
                              sizeof(double) * c->p.subj[i].v, hipMemcpyDeviceToDevice,
                              c->stream));
+  return SRM_OK;
+}
+
+srm_status srm_get_scale(srm_ctx* c, int32_t i, double* dst) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (i < 0 || i >= c->p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!dst) return fail(SRM_E_ARG, "dst is NULL");
+  HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_isd + sizeof(double) * c->p.subj[i].row0,
+                             sizeof(double) * c->p.subj[i].v, hipMemcpyDeviceToDevice,
+                             c->stream));
+  return SRM_OK;
+}
+
+// ---- checkpoint -----------------------------------------------------------
+
+namespace {
+
+struct StateHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t N, k, KP, prec;
+  int32_t fused, iters;
+  int64_t t, ldt, total_rows;
+  uint64_t vhash;
+  uint64_t bytes;
+};
+
+constexpr char kStateMagic[8] = {'S', 'R', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t kStateVersion = 1;
+
+uint64_t hash_v(const Plan& p) {  // FNV-1a over the voxel counts
+  uint64_t h = 1469598103934665603ull;
+  for (const auto& su : p.subj) {
+    uint64_t x = (uint64_t)su.v;
+    for (int b = 0; b < 8; ++b) {
+      h ^= (x >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  }
+  return h;
+}
+
+// Workspace regions carried from one iteration to the next, in blob order.
+std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p) {
+  const size_t kk = (size_t)p.KP * p.KP * 8;
+  return {{p.o_s64cur, (size_t)p.KP * p.ldt * 8}, {p.o_s64new, (size_t)p.KP * p.ldt * 8},
+          {p.o_sreccur, p.srec_bytes},            {p.o_srecnew, p.srec_bytes},
+          {p.o_sigcur, kk},                       {p.o_signew, kk},
+          {p.o_M, kk},                            {p.o_rho2, sizeof(double) * p.N},
+          {p.o_p64, (size_t)p.N * kk},            {p.o_vprev, (size_t)p.N * kk},
+          {p.o_sc, sizeof(Scalars)},              {p.o_ll, sizeof(double) * kLLCapacity}};
+}
+
+size_t state_bytes(const Plan& p) {
+  size_t n = sizeof(StateHeader) + sizeof(double) * p.N;  // header, c_i
+  for (const auto& r : state_regions(p)) n += r.second;
+  return n;
+}
+
+StateHeader make_header(const srm_ctx* c) {
+  const Plan& p = c->p;
+  StateHeader h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = kStateVersion;
+  h.N = p.N;
+  h.k = p.k;
+  h.KP = p.KP;
+  h.prec = p.prec;
+  h.fused = p.fused ? 1 : 0;
+  h.iters = c->iters;
+  h.t = p.t;
+  h.ldt = p.ldt;
+  h.total_rows = p.total_rows;
+  h.vhash = hash_v(p);
+  h.bytes = state_bytes(p);
+  return h;
+}
+
+}  // namespace
+
+srm_status srm_get_state(srm_ctx* c, void* blob, size_t* bytes) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!bytes) return fail(SRM_E_ARG, "bytes is NULL");
+  const Plan& p = c->p;
+  const size_t need = state_bytes(p);
+  if (!blob) {
+    *bytes = need;
+    return SRM_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(SRM_E_ARG, "state blob needs %zu bytes", need);
+  }
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const StateHeader h = make_header(c);
+  char* out = static_cast<char*>(blob);
+  std::memcpy(out, &h, sizeof(h));
+  size_t pos = sizeof(h);
+  HIP_OR_FAIL(hipMemcpyAsync(out + pos, c->ws + p.o_c, sizeof(double) * p.N,
+                             hipMemcpyDeviceToHost, c->stream));
+  pos += sizeof(double) * p.N;
+  for (const auto& r : state_regions(p)) {
+    HIP_OR_FAIL(hipMemcpyAsync(out + pos, c->ws + r.first, r.second, hipMemcpyDeviceToHost,
+                               c->stream));
+    pos += r.second;
+  }
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return SRM_OK;
+}
+
+srm_status srm_set_state(srm_ctx* c, const void* blob, size_t bytes) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!blob) return fail(SRM_E_ARG, "blob is NULL");
+  const Plan& p = c->p;
+  StateHeader h{};
+  if (bytes < sizeof(h)) return fail(SRM_E_ARG, "state blob too short");
+  std::memcpy(&h, blob, sizeof(h));
+  const StateHeader mine = make_header(c);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != kStateVersion)
+    return fail(SRM_E_ARG, "not an SRM state blob");
+  if (h.N != mine.N || h.k != mine.k || h.KP != mine.KP || h.prec != mine.prec ||
+      h.fused != mine.fused || h.t != mine.t || h.ldt != mine.ldt ||
+      h.total_rows != mine.total_rows || h.vhash != mine.vhash)
+    return fail(SRM_E_ARG, "state blob was taken from a different problem");
+  if (h.bytes != mine.bytes || bytes < h.bytes)
+    return fail(SRM_E_ARG, "state blob size %zu does not match %llu", bytes,
+                (unsigned long long)mine.bytes);
+  if (h.iters < 1) return fail(SRM_E_ARG, "state blob holds no iteration");
+  const char* in = static_cast<const char*>(blob);
+  size_t pos = sizeof(h);
+  std::vector<double> cdev(p.N);
+  HIP_OR_FAIL(hipMemcpyAsync(cdev.data(), c->ws + p.o_c, sizeof(double) * p.N,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  if (std::memcmp(cdev.data(), in + pos, sizeof(double) * p.N) != 0)
+    return fail(SRM_E_ARG, "state blob was taken from different data");
+  pos += sizeof(double) * p.N;
+  for (const auto& r : state_regions(p)) {
+    HIP_OR_FAIL(hipMemcpyAsync(c->ws + r.first, in + pos, r.second, hipMemcpyHostToDevice,
+                               c->stream));
+    pos += r.second;
+  }
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  c->iters = h.iters;
+  c->a_valid = false;  // A = Xhat S^T is rebuilt from S when a getter needs it
   return SRM_OK;
 }
 

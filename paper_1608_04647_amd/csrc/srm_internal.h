@@ -46,6 +46,7 @@ struct Scalars {
 
 constexpr int kLLCapacity = 1 << 16;
 
+
 // Precision codes (match srm_prec).
 enum Prec { P_FP32 = 0, P_BF16 = 1, P_BF16X2 = 2 };
 
@@ -63,9 +64,11 @@ struct ConvertArgs {
   void* xh;
   void* xl;
   double* mu;
+  double* isd;               // per row: 1/std with z-scoring, else 1
   double* rowc;
   Scalars* sc;
   int32_t prec;
+  int32_t zscore;
 };
 
 struct MArgs {
@@ -198,6 +201,7 @@ struct TArgs {
   const void* ah;
   const void* al;
   const double* mu;
+  const double* isd;
   const float* X;   // v rows, row stride ldx; columns [0, tn) used
   float* part;      // [nsplit][KP][tn]
   int64_t row0;
@@ -216,6 +220,19 @@ struct TFArgs {
   int64_t ldo;
   int32_t nsplit;
   int32_t k;
+};
+
+struct MapArgs {
+  const void* ah;
+  const void* al;
+  const double* P;   // [KP][KP] of subject j
+  const float* s;    // k x tn, row stride lds
+  float* out;        // v_j x tn, row stride ldo
+  int64_t row0;      // subject j's first global row
+  int64_t tn, lds, ldo;
+  int32_t v;
+  int32_t k;
+  int32_t prec;
 };
 
 }  // namespace srm

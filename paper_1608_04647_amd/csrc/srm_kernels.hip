@@ -32,6 +32,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "srm_internal.h"
 
 namespace srm {
@@ -150,9 +152,23 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   }
   s = wave_sum(s);
   const double mu = real ? s / (double)a.t : 0.0;
+  // Optional standardisation: population standard deviation over the
+  // samples.  A constant row keeps scale 1: the FP64 sum of equal float32
+  // values is exact, so its mean is exact and its deviations are zero.
+  double inv = 1.0;
+  if (a.zscore && real) {
+    double ss = 0.0;
+    for (int64_t c = lane; c < a.t; c += 64) {
+      const double d = (double)src[c] - mu;
+      ss += d * d;
+    }
+    ss = wave_sum(ss);
+    const double sd = sqrt(ss / (double)a.t);
+    if (sd > 0.0) inv = 1.0 / sd;
+  }
   double sq = 0.0;
   for (int64_t c = lane; c < a.ldt; c += 64) {
-    const float f = (real && c < a.t) ? (float)((double)src[c] - mu) : 0.0f;
+    const float f = (real && c < a.t) ? (float)(((double)src[c] - mu) * inv) : 0.0f;
     const int64_t o = r * a.ldt + c;
     if (a.prec == P_FP32) {
       ((float*)a.xh)[o] = f;
@@ -172,6 +188,7 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   sq = wave_sum(sq);
   if (lane == 0) {
     a.mu[r] = mu;
+    a.isd[r] = inv;
     a.rowc[r] = sq;
   }
   if (bad) a.sc->nonfinite = 1;
@@ -1207,7 +1224,8 @@ __global__ __launch_bounds__(256) void k_transform_part(TArgs a) {
   for (int u = 0; u < NJ; ++u) acc[u] = 0.f;
   if (col < a.tn) {
     for (int r = r0; r < r1; ++r) {
-      const float x = a.X[(int64_t)r * a.ldx + col] - (float)a.mu[a.row0 + r];
+      const float x = (float)(((double)a.X[(int64_t)r * a.ldx + col] - a.mu[a.row0 + r]) *
+                              a.isd[a.row0 + r]);
 #pragma unroll
       for (int u = 0; u < NJ; ++u)
         acc[u] += (float)a_elem<KP>(a.ah, a.al, a.prec, a.row0 + r, jr + 4 * u) * x;
@@ -1237,6 +1255,30 @@ __global__ __launch_bounds__(256) void k_transform_fin(TFArgs a) {
     double s = 0.0;
     for (int b = 0; b < a.k; ++b) s += a.P[j * KP + b] * Zs[b][c];
     a.out[(int64_t)j * a.ldo + col] = (float)s;
+  }
+}
+
+// Subject-to-subject mapping, second half: Y[:, cols] = A_j (P_j S_new),
+// with S_new = W_i^T (X_new - mu_i 1^T) already in `s` (k rows, stride ld).
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_map(MapArgs a) {
+  __shared__ float T[KP][64];  // P_j S_new for this block's 64 columns
+  const int c = threadIdx.x & 63, jr = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + c;
+  for (int j = jr; j < KP; j += 4) {
+    double s = 0.0;
+    if (j < a.k && col < a.tn)
+      for (int b = 0; b < a.k; ++b) s += a.P[j * KP + b] * (double)a.s[b * a.lds + col];
+    T[j][c] = (float)s;
+  }
+  __syncthreads();
+  if (col >= a.tn) return;
+  for (int64_t r = (int64_t)blockIdx.y * 4 + jr; r < a.v; r += (int64_t)gridDim.y * 4) {
+    float acc = 0.f;
+    for (int b = 0; b < a.k; ++b)
+      acc += (float)a_elem<KP>(a.ah, a.al, a.prec, a.row0 + r, b) * T[b][c];
+    a.out[r * a.ldo + col] = acc;
   }
 }
 
@@ -1357,6 +1399,13 @@ hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
     default: return hipErrorInvalidValue;
   }
 #undef SRM_FUSED_NW
+  return hipGetLastError();
+}
+
+hipError_t launch_map(hipStream_t st, int kp, const MapArgs& a) {
+  const int ncol = (int)((a.tn + 63) / 64);
+  const int nrow = (int)std::min<int64_t>(1024, (a.v + 3) / 4);
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_map<KP>), dim3(ncol, nrow), dim3(256), 0, st, a));
   return hipGetLastError();
 }
 

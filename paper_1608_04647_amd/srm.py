@@ -28,7 +28,7 @@ SRM_OK, SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_HIP, SRM_E_RANK, SRM_E_NOTPD, \
 STATUS_NAMES = {0: "SRM_OK", 1: "SRM_E_ARG", 2: "SRM_E_WORKSPACE", 3: "SRM_E_HIP",
                 4: "SRM_E_RANK", 5: "SRM_E_NOTPD", 6: "SRM_E_NONFINITE", 7: "SRM_E_STATE"}
 PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2}
-SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST = 1, 2, 4, 8
+SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE = 1, 2, 4, 8, 16
 
 
 class SrmDesc(ctypes.Structure):
@@ -47,11 +47,15 @@ _sigs = {
     "srm_fit": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_profile": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_transform": (ctypes.c_int, [_P, _I32, _P, _I64, _P]),
+    "srm_map": (ctypes.c_int, [_P, _I32, _I32, _P, _I64, _P]),
     "srm_get_w": (ctypes.c_int, [_P, _I32, _P]),
     "srm_get_s": (ctypes.c_int, [_P, _P]),
     "srm_get_rho2": (ctypes.c_int, [_P, _DP]),
     "srm_get_sigma_s": (ctypes.c_int, [_P, _DP]),
     "srm_get_mu": (ctypes.c_int, [_P, _I32, _P]),
+    "srm_get_scale": (ctypes.c_int, [_P, _I32, _P]),
+    "srm_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(_SZ)]),
+    "srm_set_state": (ctypes.c_int, [_P, _P, _SZ]),
     "srm_get_loglik": (ctypes.c_int, [_P, _DP, _I32, ctypes.POINTER(_I32)]),
     "srm_iterations": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     "srm_last_error": (ctypes.c_char_p, []),
@@ -111,16 +115,18 @@ class SRM:
     place, anything else is uploaded (or, with stream_from_host, streamed
     through the library's staging area one subject at a time).  W0: list of
     N float64 host arrays (v_i x k, orthonormal columns); None draws random
-    orthonormal maps."""
+    orthonormal maps.  zscore standardises each voxel after demeaning."""
 
     def __init__(self, X, k: int, prec: str = "fp32", W0=None, flags: int = 0,
-                 seed: int = 0, stream_from_host: bool = False):
+                 seed: int = 0, stream_from_host: bool = False, zscore: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise SRMError(SRM_E_HIP, "no HIP device visible")
         self._torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
         xs = []
+        if zscore:
+            flags |= SRM_ZSCORE
         if stream_from_host:
             flags |= SRM_X_HOST
             for x in X:
@@ -207,6 +213,24 @@ class SRM:
         self._sync()
         return out
 
+    def scale(self, i: int):
+        out = self._torch.empty(self.v[i], dtype=self._torch.float64, device=self._dev)
+        _check(_lib.srm_get_scale(self._ctx, int(i), _P(out.data_ptr())))
+        self._sync()
+        return out
+
+    def get_state(self) -> bytes:
+        """Checkpoint of everything an iteration carries to the next."""
+        n = _SZ()
+        _check(_lib.srm_get_state(self._ctx, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_lib.srm_get_state(self._ctx, ctypes.cast(buf, _P), ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(_lib.srm_set_state(self._ctx, ctypes.cast(buf, _P), len(blob)))
+
     def loglik(self) -> np.ndarray:
         cnt = _I32()
         _check(_lib.srm_get_loglik(self._ctx, None, 0, ctypes.byref(cnt)))
@@ -229,6 +253,20 @@ class SRM:
         self._sync()
         _check(_lib.srm_transform(self._ctx, int(i), _P(x.data_ptr()), int(x.shape[1]),
                                   _P(out.data_ptr())))
+        self._sync()
+        return out
+
+    def map(self, i: int, j: int, X_new):
+        """Subject i's samples mapped into subject j's (demeaned) voxel space:
+        W_j W_i^T (X_new - mu_i 1^T)."""
+        torch = self._torch
+        x = X_new if (isinstance(X_new, torch.Tensor) and X_new.is_cuda) else \
+            torch.as_tensor(np.ascontiguousarray(X_new, dtype=np.float32)).to(self._dev)
+        x = x.to(torch.float32).contiguous()
+        out = torch.empty((self.v[j], x.shape[1]), dtype=torch.float32, device=self._dev)
+        self._sync()
+        _check(_lib.srm_map(self._ctx, int(i), int(j), _P(x.data_ptr()), int(x.shape[1]),
+                            _P(out.data_ptr())))
         self._sync()
         return out
 

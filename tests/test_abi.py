@@ -100,6 +100,12 @@ def test_calls_on_null_context():
     assert lib.srm_fit(None, 1, None) == srm.SRM_E_ARG
     assert lib.srm_em_step(None, None) == srm.SRM_E_ARG
     assert lib.srm_get_w(None, 0, None) == srm.SRM_E_ARG
+    assert lib.srm_transform(None, 0, None, 1, None) == srm.SRM_E_ARG
+    assert lib.srm_map(None, 0, 1, None, 1, None) == srm.SRM_E_ARG
+    assert lib.srm_get_scale(None, 0, None) == srm.SRM_E_ARG
+    n = ctypes.c_size_t(0)
+    assert lib.srm_get_state(None, None, ctypes.byref(n)) == srm.SRM_E_ARG
+    assert lib.srm_set_state(None, None, 0) == srm.SRM_E_ARG
     lib.srm_free(None)
 
 

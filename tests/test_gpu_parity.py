@@ -154,6 +154,103 @@ def test_transform_matches_oracle_projection(prec):
         assert np.allclose(mu, ora["mu"][i], rtol=0, atol=1e-6)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_map_matches_oracle(prec):
+    """Subject-to-subject mapping W_j W_i^T (X_new - mu_i 1^T) (Sec. II-A), with
+    enough columns to take several scratch chunks, and the i == j case."""
+    srm = _srm()
+    w = CASES["ragged"]
+    d = synth.generate(w, seed=3)
+    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"])
+    g.fit(w.n_iter)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    rng = np.random.default_rng(1)
+    for i, j, tn in ((0, 3, 300), (3, 1, 1), (2, 2, 77)):
+        Xn = rng.standard_normal((d["X"][i].shape[0], tn)).astype(np.float32)
+        out = g.map(i, j, Xn).cpu().numpy().astype(np.float64)
+        assert out.shape == (d["X"][j].shape[0], tn)
+        ref = ora["W"][j] @ (ora["W"][i].T @ (Xn.astype(np.float64) - ora["mu"][i][:, None]))
+        err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+        _say(f"[errors] map {prec} {i}->{j} t={tn}: {err:.2e}")
+        assert err <= BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_zscore_matches_oracle(prec):
+    """Standardised input (Sec. IV-A, reading R12): voxels given very different
+    scales and offsets, one constant voxel; the fit, the stored mean and scale
+    and the projection of held-out samples follow the oracle on Z."""
+    srm = _srm()
+    w = CASES["ragged"]
+    d = synth.generate(w, seed=4)
+    rng = np.random.default_rng(9)
+    X = []
+    for x in d["X"]:
+        a = rng.uniform(0.05, 40.0, (x.shape[0], 1))
+        b = rng.normal(0.0, 100.0, (x.shape[0], 1))
+        X.append((x * a + b).astype(np.float32))
+    X[1][5, :] = np.float32(0.1)
+    g = srm.SRM(X, w.k, prec=prec, W0=d["W0"], zscore=True)
+    g.fit(w.n_iter)
+    zs = [oracle.zscore(x) for x in X]
+    ora = oracle.em_fit([z[1] for z in zs], w.k, w.n_iter, d["W0"], final_loglik=True,
+                        demeaned=True)
+    e = compare(g, ora, w.n_subjects)
+    _say(f"[errors] zscore/{prec}: " + ", ".join(f"{k}={v:.2e}" for k, v in e.items()
+                                                 if k != "ll_gpu"))
+    assert e["S"] <= BAR[prec] and e["W"] <= BAR[prec]
+    assert e["rho2"] <= BAR[prec] and e["Sigma_s"] <= BAR[prec]
+    for i in range(w.n_subjects):
+        assert np.allclose(g.mu(i).cpu().numpy(), zs[i][0], rtol=1e-12, atol=1e-9)
+        assert np.allclose(g.scale(i).cpu().numpy(), zs[i][2], rtol=1e-12, atol=0)
+    assert g.scale(1).cpu().numpy()[5] == 1.0
+    Xn = (rng.standard_normal((X[2].shape[0], 40)) * 10).astype(np.float32)
+    out = g.transform(2, Xn).cpu().numpy().astype(np.float64)
+    ref = ora["W"][2].T @ ((Xn.astype(np.float64) - zs[2][0][:, None]) * zs[2][2][:, None])
+    lhs = g.W(2).cpu().numpy().astype(np.float64) @ out
+    err = np.linalg.norm(lhs - ora["W"][2] @ ref) / np.linalg.norm(ora["W"][2] @ ref)
+    assert err <= BAR[prec]
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_checkpoint_resume_is_bitwise(flags):
+    """A fit stopped after 3 iterations, saved, restored into a fresh context on
+    the same data and continued equals the uninterrupted 6-iteration fit."""
+    srm = _srm()
+    w = CASES["slices"]
+    d = synth.generate(w, seed=6)
+    a = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+    a.fit(6)
+    b = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+    with pytest.raises(srm.SRMError) as ei:
+        b.get_state()
+    assert ei.value.status == srm.SRM_E_STATE
+    b.fit(3)
+    blob = b.get_state()
+    w4 = b.W(4).cpu().numpy()
+    b.close()
+    c = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+    c.set_state(blob)
+    assert c.iterations() == 3
+    assert np.array_equal(c.W(4).cpu().numpy(), w4)
+    c.fit(3)
+    assert c.iterations() == 6
+    assert np.array_equal(a.S().cpu().numpy(), c.S().cpu().numpy())
+    assert np.array_equal(a.rho2(), c.rho2())
+    assert np.array_equal(a.sigma_s(), c.sigma_s())
+    assert np.array_equal(a.loglik(), c.loglik())
+    for i in (0, 5):
+        assert np.array_equal(a.W(i).cpu().numpy(), c.W(i).cpu().numpy())
+    # a blob is refused by a context on other data, and when truncated
+    X2 = [x.copy() for x in d["X"]]
+    X2[0][0, 0] += 1.0
+    e = srm.SRM(X2, w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+    for bad in (blob, blob[:-8]):
+        with pytest.raises(srm.SRMError) as ei:
+            e.set_state(bad)
+        assert ei.value.status == srm.SRM_E_ARG
+
+
 def test_nonfinite_input_is_rejected():
     srm = _srm()
     w = CASES["tiny"]

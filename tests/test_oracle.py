@@ -276,3 +276,31 @@ def test_flop_model_counts():
     economy SVD counted as Householder QR."""
     f = oracle.flop_model([1000], 100, 10)
     assert f == 2 * 2 * 1000 * 100 * 10 + 2 * 1000 * 100 + 2 * 1000 * 100 - 2 / 3 * 1000
+
+
+def test_p12_zscore_matches_scipy_and_standardises():
+    """Sec. IV-A data standardisation (reading R12) against scipy.stats.zscore
+    (population standard deviation), with the per-voxel invariants it fixes."""
+    from scipy import stats
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((37, 29)) * rng.uniform(0.1, 30, (37, 1)) + rng.normal(0, 50, (37, 1))
+    mu, Z, scale = oracle.zscore(X)
+    assert np.allclose(Z, stats.zscore(X, axis=1), rtol=0, atol=1e-12)
+    assert np.allclose(mu, X.mean(axis=1), rtol=0, atol=1e-12)
+    assert np.allclose(Z.mean(axis=1), 0, atol=1e-13)
+    assert np.allclose((Z * Z).mean(axis=1), 1, rtol=1e-13)
+    assert np.allclose(scale, 1.0 / X.std(axis=1), rtol=1e-13)
+    # positive affine maps of a voxel leave its standardised series unchanged
+    _, Z2, _ = oracle.zscore(3.5 * X - 7.0)
+    assert np.allclose(Z2, Z, atol=1e-12)
+
+
+def test_p12_zscore_constant_voxels_are_only_demeaned():
+    """A constant voxel has no scale to remove: it stays at zero with scale 1
+    (for float32 data its FP64 mean is exact, 0.1 included)."""
+    X = np.vstack([np.full(50, 0.1), np.zeros(50), np.full(50, -3.0),
+                   np.arange(50.0)]).astype(np.float32)
+    mu, Z, scale = oracle.zscore(X)
+    assert np.array_equal(scale[:3], [1.0, 1.0, 1.0])
+    assert np.all(Z[:3] == 0.0)
+    assert np.isclose(scale[3], 1.0 / np.arange(50.0).std())

@@ -36,6 +36,9 @@ MUTATIONS = {
     "loglik: v_i weight dropped": ("t * float(np.sum(v * np.log(rho2)))", "t * float(np.sum(np.log(rho2)))"),
     "Eq.4: U instead of U V^T": ("return U @ Vt, float(sig.sum())", "return U, float(sig.sum())"),
     "init: Sigma_s starts at 2I": ("Sigma_s = np.eye(k)  # R3", "Sigma_s = 2.0 * np.eye(k)  # R3"),
+    "z-score: sample std (1/(t-1))": ("sd = np.sqrt(np.mean(D * D, axis=1))",
+                                      "sd = np.sqrt(np.sum(D * D, axis=1) / (X.shape[1] - 1))"),
+    "z-score: constant voxels not kept at zero": ("keep = sd > 0", "keep = sd >= 0"),
 }
 
 
