@@ -81,12 +81,21 @@ enum {
   SRM_X_HOST = 8u,      /* srm_init's X[i] are host pointers: each subject is
                            uploaded through a staging area in the workspace and
                            converted there (no full FP32 copy on the device)  */
-  SRM_ZSCORE = 16u      /* standardise each voxel (the z-score preprocessing of
+  SRM_ZSCORE = 16u,     /* standardise each voxel (the z-score preprocessing of
                            the paper's implementation, Sec. IV-A): after the
                            mean, divide by the population standard deviation
                            over the t samples (1/t).  A constant voxel is only
                            demeaned.  srm_transform and srm_map apply the same
                            per-voxel scale.                                    */
+  SRM_GRAM = 32u        /* sample-space iteration (the Discussion's change of
+                           complexity from voxels to samples): srm_init forms
+                           G_i = Xhat_i^T Xhat_i (t x t, FP64, N t^2 8 bytes of
+                           workspace) in one pass over the data; each iteration
+                           then uses A_i^T Xhat_i = S G_i and A_i^T A_i =
+                           S G_i S^T and reads no voxel data.  The same EM
+                           iterate as the streamed sweep up to rounding; pays
+                           off when t is well below the voxel counts.  At most
+                           65535 subjects.                                    */
 };
 
 typedef struct {
@@ -140,6 +149,7 @@ srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
  *  SRM_PHASE_EREDUCE   Y = sum_i rho_i^-2 W_i^T Xhat_i (Eq. 10 reduction)
  *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11)
  *  SRM_PHASE_FUSED     one-pass sweep forming A, A^T Xhat and A^T A together
+ *  SRM_PHASE_GRAM      sample-space products S G_i and S G_i S^T (SRM_GRAM)
  *                      (replaces MPHASE + EPHASE where it applies) */
 enum {
   SRM_PHASE_MPHASE = 0,
@@ -148,7 +158,8 @@ enum {
   SRM_PHASE_EREDUCE = 3,
   SRM_PHASE_POSTERIOR = 4,
   SRM_PHASE_FUSED = 5,
-  SRM_NPHASE = 6
+  SRM_PHASE_GRAM = 6,
+  SRM_NPHASE = 7
 };
 
 /* Runs n_iter iterations like srm_fit but with direct kernel launches, each

@@ -33,6 +33,8 @@ hipError_t launch_get_w(hipStream_t, int, const WArgs&);
 hipError_t launch_transform(hipStream_t, int, int, const TArgs&, const TFArgs&);
 hipError_t occupancy_mphase(int, int, int*);
 hipError_t launch_map(hipStream_t, int, const MapArgs&);
+hipError_t launch_gram_build(hipStream_t, int, int, int, const GBArgs&);
+hipError_t launch_gram_iter(hipStream_t, int, int, const GZArgs&, const GSArgs&);
 bool fused_supported(int kp, int prec, int64_t ldt);
 hipError_t launch_fused(hipStream_t, int, int, int64_t, int, const FusedArgs&);
 hipError_t occupancy_ephase(int, int, int*);
@@ -76,6 +78,8 @@ struct Plan {
   int64_t t = 0, ldt = 0, total_rows = 0;
   int npanel = 0, nranges = 0, nslices = 0;
   bool fused = false;
+  bool gram = false;  // sample-space iteration on G_i = Xhat_i^T Xhat_i
+  int nq = 0;         // 64-TR column tiles of G_i
   int rct = 0, ncol_r = 0, gsub = 0, ngrp = 0;
   int nblk_s = 0;
   std::vector<Subject> subj;
@@ -87,7 +91,8 @@ struct Plan {
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
          o_prepwork = 0, o_polwork = 0, o_vprev = 0, o_sc = 0, o_ll = 0, o_subj = 0,
-         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0;
+         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0,
+         o_G = 0, o_gz = 0, o_subjg = 0;
   size_t stage_bytes = 0;
   size_t total = 0;
   size_t arec_bytes = 0, srec_bytes = 0, zpart_bytes = 0;
@@ -126,7 +131,10 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.t = d->t;
   p.ldt = round_up(d->t, kColPad);
   // The one-pass sweep runs whole 128-TR groups (pairs of 64-TR waves).
-  if (fused_supported(p.KP, p.prec, round_up(d->t, 128)) && !(d->flags & SRM_TWO_PASS))
+  p.gram = (d->flags & SRM_GRAM) != 0;
+  if (p.gram && p.N > 65535) return fail(SRM_E_ARG, "SRM_GRAM supports at most 65535 subjects");
+  if (fused_supported(p.KP, p.prec, round_up(d->t, 128)) &&
+      !(d->flags & (SRM_TWO_PASS | SRM_GRAM)))
     p.ldt = round_up(d->t, 128);
   p.subj.resize(p.N);
   int64_t row = 0;
@@ -139,7 +147,7 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.total_rows = row;
   // E-phase: equal row ranges (multiples of 32 rows) split at subject ends.
   p.npanel = (int)((p.ldt + 255) / 256);
-  p.fused = fused_supported(p.KP, p.prec, p.ldt) && !(d->flags & SRM_TWO_PASS);
+  p.fused = fused_supported(p.KP, p.prec, p.ldt) && !(d->flags & (SRM_TWO_PASS | SRM_GRAM));
   const int64_t nblk32 = p.total_rows / 32;
   p.nranges = (int)std::max<int64_t>(
       1, std::min<int64_t>(nblk32, p.fused ? kFusedWGs : kEphaseWGs / p.npanel));
@@ -218,6 +226,12 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_srow0 = take(sizeof(int64_t) * p.N);
   p.o_sv = take(sizeof(int32_t) * p.N);
   p.o_xptr = take(sizeof(void*) * p.N);
+  if (p.gram) {
+    p.nq = (int)(p.ldt / 64);
+    p.o_G = take((size_t)p.N * p.ldt * p.ldt * 8);
+    p.o_gz = take((size_t)p.N * p.nq * p.KP * p.KP * 8);
+    p.o_subjg = take(sizeof(Subject) * p.N);
+  }
   if (d->flags & SRM_X_HOST) {  // staging for one subject's FP32 rows at a time
     int64_t vmax = 0;
     for (int i = 0; i < p.N; ++i) vmax = std::max<int64_t>(vmax, d->v[i]);
@@ -414,14 +428,16 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
     Phase ph(c, SRM_PHASE_EPHASE);
     if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
   }
+  // The sample-space iteration keeps each subject's partials in slice i.
+  const size_t o_tab = (p.gram && with_polar) ? p.o_subjg : p.o_subj;
   if (with_polar) {
-    QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_c),
+    QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(o_tab), c->at<double>(p.o_c),
              c->at<double>(p.o_rho2), c->at<double>(p.o_p64), c->at<double>(p.o_polwork),
              c->at<double>(p.o_vprev), c->at<Scalars>(p.o_sc), p.k, p.t};
     Phase ph(c, SRM_PHASE_POLAR);
     if ((e = launch_polar(st, p.KP, p.N, qa)) != hipSuccess) return e;
   }
-  RArgs ra{c->at<float>(p.o_zpart), c->at<Subject>(p.o_subj), c->at<double>(p.o_p64),
+  RArgs ra{c->at<float>(p.o_zpart), c->at<Subject>(o_tab), c->at<double>(p.o_p64),
            c->at<double>(p.o_rho2), c->at<double>(p.o_ygrp), p.N, p.gsub, p.ldt};
   {
     Phase ph(c, SRM_PHASE_EREDUCE);
@@ -457,6 +473,17 @@ hipError_t enqueue_iteration(srm_ctx* c) {
               c->at<double>(p.o_signew), c->at<double>(p.o_sigcur), c->at<Scalars>(p.o_sc),
               (int64_t)p.KP * p.ldt, (int64_t)(p.srec_bytes / 16), p.KP * p.KP};
   if ((e = launch_copy_state(st, ca)) != hipSuccess) return e;
+  if (p.gram) {
+    GZArgs za{c->at<double>(p.o_G), c->at<double>(p.o_s64cur), c->at<float>(p.o_zpart),
+              c->at<double>(p.o_gz), p.t, p.ldt, p.nq, p.k};
+    GSArgs ga{c->at<double>(p.o_gz), c->at<float>(p.o_gpart), p.nq};
+    {
+      Phase ph(c, SRM_PHASE_GRAM);
+      if ((e = launch_gram_iter(st, p.KP, p.N, za, ga)) != hipSuccess) return e;
+    }
+    c->a_valid = false;
+    return enqueue_estep(c, true, /*stream_pass=*/false);
+  }
   if (p.fused) {
     FusedArgs fa{q.xh, q.xl, q.shc, q.slc, c->at<Slice>(p.o_slices), c->at<int32_t>(p.o_rs),
                  c->at<float>(p.o_zpart), c->at<float>(p.o_gpart), p.ldt};
@@ -520,6 +547,73 @@ srm_status read_scalars(srm_ctx* c, Scalars* s) {
     return fail(SRM_E_NOTPD, "Sigma_s or Sigma_s^-1 + rho0 I is not positive definite");
   if (s->status != 0) return fail((srm_status)s->status, "device error %d", s->status);
   return SRM_OK;
+}
+
+}  // namespace
+
+// ---- checkpoint -----------------------------------------------------------
+
+namespace {
+
+struct StateHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t N, k, KP, prec;
+  int32_t fused, iters;
+  int64_t t, ldt, total_rows;
+  uint64_t vhash;
+  uint64_t bytes;
+};
+
+constexpr char kStateMagic[8] = {'S', 'R', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t kStateVersion = 1;
+
+uint64_t hash_v(const Plan& p) {  // FNV-1a over the voxel counts
+  uint64_t h = 1469598103934665603ull;
+  for (const auto& su : p.subj) {
+    uint64_t x = (uint64_t)su.v;
+    for (int b = 0; b < 8; ++b) {
+      h ^= (x >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  }
+  return h;
+}
+
+// Workspace regions carried from one iteration to the next, in blob order.
+std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p) {
+  const size_t kk = (size_t)p.KP * p.KP * 8;
+  return {{p.o_s64cur, (size_t)p.KP * p.ldt * 8}, {p.o_s64new, (size_t)p.KP * p.ldt * 8},
+          {p.o_sreccur, p.srec_bytes},            {p.o_srecnew, p.srec_bytes},
+          {p.o_sigcur, kk},                       {p.o_signew, kk},
+          {p.o_M, kk},                            {p.o_rho2, sizeof(double) * p.N},
+          {p.o_p64, (size_t)p.N * kk},            {p.o_vprev, (size_t)p.N * kk},
+          {p.o_sc, sizeof(Scalars)},              {p.o_ll, sizeof(double) * kLLCapacity}};
+}
+
+size_t state_bytes(const Plan& p) {
+  size_t n = sizeof(StateHeader) + sizeof(double) * p.N;  // header, c_i
+  for (const auto& r : state_regions(p)) n += r.second;
+  return n;
+}
+
+StateHeader make_header(const srm_ctx* c) {
+  const Plan& p = c->p;
+  StateHeader h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = kStateVersion;
+  h.N = p.N;
+  h.k = p.k;
+  h.KP = p.KP;
+  h.prec = p.prec;
+  h.fused = p.fused ? 1 : (p.gram ? 2 : 0);
+  h.iters = c->iters;
+  h.t = p.t;
+  h.ldt = p.ldt;
+  h.total_rows = p.total_rows;
+  h.vhash = hash_v(p);
+  h.bytes = state_bytes(p);
+  return h;
 }
 
 }  // namespace
@@ -657,6 +751,22 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(SRM_E_HIP, "conversion failed"));
   if (chk.nonfinite) return bail(fail(SRM_E_NONFINITE, "X contains NaN or Inf"));
+
+  if (P.gram) {
+    // Per-subject sample Gram matrices, and a subject table in which subject
+    // i's E-phase partial is slice i (the sample-space iteration writes one).
+    std::vector<Subject> sg(P.subj);
+    for (int i = 0; i < P.N; ++i) {
+      sg[i].s_beg = i;
+      sg[i].s_end = i + 1;
+    }
+    if (up(P.o_subjg, sg.data(), sizeof(Subject) * P.N) != hipSuccess)
+      return bail(fail(SRM_E_HIP, "upload of tables failed"));
+    const int nt = (int)(P.ldt / 64);
+    GBArgs gb{q.xh, q.xl, c->at<Subject>(P.o_subj), c->at<double>(P.o_G), P.ldt, nt};
+    if (launch_gram_build(c->stream, P.prec, nt * (nt + 1) / 2, P.N, gb) != hipSuccess)
+      return bail(fail(SRM_E_HIP, "Gram launch failed"));
+  }
 
   // First E-step with W_i = W0_i (P = I), rho^2 = 1, Sigma_s = I.
   if (enqueue_estep(c, false, true) != hipSuccess)
@@ -876,72 +986,6 @@ srm_status srm_get_scale(srm_ctx* c, int32_t i, double* dst) {
   return SRM_OK;
 }
 
-// ---- checkpoint -----------------------------------------------------------
-
-namespace {
-
-struct StateHeader {
-  char magic[8];
-  uint32_t version;
-  int32_t N, k, KP, prec;
-  int32_t fused, iters;
-  int64_t t, ldt, total_rows;
-  uint64_t vhash;
-  uint64_t bytes;
-};
-
-constexpr char kStateMagic[8] = {'S', 'R', 'M', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kStateVersion = 1;
-
-uint64_t hash_v(const Plan& p) {  // FNV-1a over the voxel counts
-  uint64_t h = 1469598103934665603ull;
-  for (const auto& su : p.subj) {
-    uint64_t x = (uint64_t)su.v;
-    for (int b = 0; b < 8; ++b) {
-      h ^= (x >> (8 * b)) & 0xff;
-      h *= 1099511628211ull;
-    }
-  }
-  return h;
-}
-
-// Workspace regions carried from one iteration to the next, in blob order.
-std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p) {
-  const size_t kk = (size_t)p.KP * p.KP * 8;
-  return {{p.o_s64cur, (size_t)p.KP * p.ldt * 8}, {p.o_s64new, (size_t)p.KP * p.ldt * 8},
-          {p.o_sreccur, p.srec_bytes},            {p.o_srecnew, p.srec_bytes},
-          {p.o_sigcur, kk},                       {p.o_signew, kk},
-          {p.o_M, kk},                            {p.o_rho2, sizeof(double) * p.N},
-          {p.o_p64, (size_t)p.N * kk},            {p.o_vprev, (size_t)p.N * kk},
-          {p.o_sc, sizeof(Scalars)},              {p.o_ll, sizeof(double) * kLLCapacity}};
-}
-
-size_t state_bytes(const Plan& p) {
-  size_t n = sizeof(StateHeader) + sizeof(double) * p.N;  // header, c_i
-  for (const auto& r : state_regions(p)) n += r.second;
-  return n;
-}
-
-StateHeader make_header(const srm_ctx* c) {
-  const Plan& p = c->p;
-  StateHeader h{};
-  std::memcpy(h.magic, kStateMagic, 8);
-  h.version = kStateVersion;
-  h.N = p.N;
-  h.k = p.k;
-  h.KP = p.KP;
-  h.prec = p.prec;
-  h.fused = p.fused ? 1 : 0;
-  h.iters = c->iters;
-  h.t = p.t;
-  h.ldt = p.ldt;
-  h.total_rows = p.total_rows;
-  h.vhash = hash_v(p);
-  h.bytes = state_bytes(p);
-  return h;
-}
-
-}  // namespace
 
 srm_status srm_get_state(srm_ctx* c, void* blob, size_t* bytes) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");

@@ -235,4 +235,32 @@ struct MapArgs {
   int32_t prec;
 };
 
+// Sample-space (voxel-free) iteration: G_i = Xhat_i^T Xhat_i, built once.
+struct GBArgs {
+  const void* xh;
+  const void* xl;
+  const Subject* subj;
+  double* G;        // [N][ldt][ldt]
+  int64_t ldt;
+  int32_t nt;       // ldt / 64 column tiles
+};
+
+// Per iteration: Z_i = S G_i (into the subject's E-phase partial) and the
+// per-column-tile partials of Z_i S^T.
+struct GZArgs {
+  const double* G;
+  const double* S;  // [KP][ldt] FP64 S of the current posterior
+  float* zpart;     // [N][KP][ldt]
+  double* gz;       // [N][nq][KP][KP]
+  int64_t t, ldt;
+  int32_t nq;
+  int32_t k;
+};
+
+struct GSArgs {
+  const double* gz;
+  float* gpart;     // [N][KP][KP]
+  int32_t nq;
+};
+
 }  // namespace srm

@@ -1283,6 +1283,172 @@ __global__ __launch_bounds__(256) void k_map(MapArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Sample-space iteration (the voxel-to-sample change of complexity of the
+// Discussion): with A_i = Xhat_i S^T,
+//   A_i^T Xhat_i = S G_i   and   A_i^T A_i = S G_i S^T,   G_i = Xhat_i^T Xhat_i,
+// so after one pass that forms G_i the iteration never reads Xhat again.
+// ---------------------------------------------------------------------------
+
+// G_i tile (64 x 64 TRs) for an upper tile pair (ta <= tb), mirrored below
+// the diagonal.  Contraction over the subject's rows with FP32 matrix cores,
+// 256-row chunks flushed into FP64 accumulators; the four waves take
+// interleaved 16-row steps and are summed in a fixed order.
+template <int PREC>
+__device__ __forceinline__ float x_at(const GBArgs& a, int64_t o) {
+  if constexpr (PREC == P_FP32) return ((const float*)a.xh)[o];
+  float v = bf2f(((const uint16_t*)a.xh)[o]);
+  if constexpr (PREC == P_BF16X2) v += bf2f(((const uint16_t*)a.xl)[o]);
+  return v;  // hi + lo is exact in FP32
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gram_build(GBArgs a) {
+  __shared__ double L[64][65];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  int idx = blockIdx.x, ta = 0;
+  while (idx >= a.nt - ta) {
+    idx -= a.nt - ta;
+    ++ta;
+  }
+  const int tb = ta + idx;
+  const Subject su = a.subj[blockIdx.y];
+  const int64_t ca = 64 * (int64_t)ta, cb = 64 * (int64_t)tb;
+  double acc64[4][4][4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc64[mb][nb][e] = 0.0;
+  const int nstep = su.vp / 16;
+  for (int s0 = wave; s0 < nstep; s0 += 4 * 16) {
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int s1 = min(nstep, s0 + 4 * 16);
+    for (int st = s0; st < s1; st += 4) {
+      const int64_t r = su.row0 + 16 * (int64_t)st + 4 * g;
+      float xa[4][4], xb[4][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) xa[mb][e] = x_at<PREC>(a, (r + e) * a.ldt + ca + 16 * mb + n);
+      if (ta != tb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb)
+            xb[nb][e] = x_at<PREC>(a, (r + e) * a.ldt + cb + 16 * nb + n);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) xb[nb][e] = xa[nb][e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma_f32(xa[mb][e], xb[nb][e], acc[mb][nb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc64[mb][nb][e] += (double)acc[mb][nb][e];
+  }
+  // Accumulator lane (n, g) element e holds G[ca + 16 mb + 4 g + e][cb + 16 nb + n].
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            double& d = L[16 * mb + 4 * g + e][16 * nb + n];
+            d = (w == 0 ? 0.0 : d) + acc64[mb][nb][e];
+          }
+    }
+    __syncthreads();
+  }
+  double* G = a.G + (int64_t)blockIdx.y * a.ldt * a.ldt;
+  const int c = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < 64; p += 4) G[(ca + p) * a.ldt + cb + c] = L[p][c];
+  if (ta != tb)
+    for (int p = threadIdx.x >> 6; p < 64; p += 4) G[(cb + p) * a.ldt + ca + c] = L[c][p];
+}
+
+// Z_i[:, q-tile] = S G_i[:, q-tile] in FP64 (k x 64 per workgroup), stored in
+// the subject's E-phase partial, and the tile's share of Z_i S^T.
+template <int KP>
+__global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
+  constexpr int NJ = KP / 4;
+  constexpr int PC = 32;  // TRs per staged chunk
+  constexpr int SM1 = PC * 64 + KP * (PC + 1), SM2 = 2 * KP * 65;
+  __shared__ double sm[SM1 > SM2 ? SM1 : SM2];
+  const int c = threadIdx.x & 63, jr = threadIdx.x >> 6;
+  const int qt = blockIdx.x, i = blockIdx.y;
+  const int64_t q0 = 64 * (int64_t)qt;
+  const double* G = a.G + (int64_t)i * a.ldt * a.ldt;
+  double acc[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) acc[u] = 0.0;
+  double (*Gs)[64] = reinterpret_cast<double (*)[64]>(sm);            // [PC][64]
+  double (*Ss)[PC + 1] = reinterpret_cast<double (*)[PC + 1]>(sm + PC * 64);  // [KP][PC+1]
+  for (int64_t p0 = 0; p0 < a.t; p0 += PC) {
+    for (int pp = jr; pp < PC; pp += 4) Gs[pp][c] = G[(p0 + pp) * a.ldt + q0 + c];
+    for (int idx = threadIdx.x; idx < KP * PC; idx += 256) {
+      const int j = idx / PC, pp = idx % PC;
+      Ss[j][pp] = (j < a.k && p0 + pp < a.t) ? a.S[(int64_t)j * a.ldt + p0 + pp] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int pp = 0; pp < PC; ++pp) {
+      const double gv = Gs[pp][c];
+#pragma unroll
+      for (int u = 0; u < NJ; ++u) acc[u] += Ss[jr + 4 * u][pp] * gv;
+    }
+    __syncthreads();
+  }
+  float* Z = a.zpart + (int64_t)i * KP * a.ldt;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) Z[(int64_t)(jr + 4 * u) * a.ldt + q0 + c] = (float)acc[u];
+  // Gram share: sum over this tile's 64 TRs of Z[j][q] S[l][q].
+  double (*Zt)[65] = reinterpret_cast<double (*)[65]>(sm);
+  double (*St)[65] = reinterpret_cast<double (*)[65]>(sm + KP * 65);
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) Zt[jr + 4 * u][c] = acc[u];
+  for (int l = jr; l < KP; l += 4)
+    St[l][c] = (l < a.k && q0 + c < a.t) ? a.S[(int64_t)l * a.ldt + q0 + c] : 0.0;
+  __syncthreads();
+  double* out = a.gz + ((int64_t)i * a.nq + qt) * KP * KP;
+  for (int idx = threadIdx.x; idx < KP * KP; idx += 256) {
+    const int j = idx / KP, l = idx % KP;
+    double s = 0.0;
+#pragma unroll 8
+    for (int cc = 0; cc < 64; ++cc) s += Zt[j][cc] * St[l][cc];
+    out[idx] = s;
+  }
+}
+
+// gpart[i] = sum over column tiles of the Gram shares (fixed order).
+template <int KP>
+__global__ __launch_bounds__(256) void k_gram_gsum(GSArgs a) {
+  const int i = blockIdx.x;
+  for (int idx = threadIdx.x; idx < KP * KP; idx += 256) {
+    double s = 0.0;
+    for (int qt = 0; qt < a.nq; ++qt) s += a.gz[((int64_t)i * a.nq + qt) * KP * KP + idx];
+    a.gpart[(int64_t)i * KP * KP + idx] = (float)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers (template dispatch on K padding and storage format).
 // ---------------------------------------------------------------------------
 #define SRM_KP_SWITCH(KPV, ...)                          \
@@ -1399,6 +1565,19 @@ hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
     default: return hipErrorInvalidValue;
   }
 #undef SRM_FUSED_NW
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_build(hipStream_t st, int prec, int npairs, int N, const GBArgs& a) {
+  SRM_PREC_SWITCH(prec, hipLaunchKernelGGL((k_gram_build<PR>), dim3(npairs, N), dim3(256), 0,
+                                           st, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_iter(hipStream_t st, int kp, int N, const GZArgs& z, const GSArgs& g) {
+  SRM_KP_SWITCH(kp,
+      hipLaunchKernelGGL((k_gram_z<KP>), dim3(z.nq, N), dim3(256), 0, st, z);
+      hipLaunchKernelGGL((k_gram_gsum<KP>), dim3(N), dim3(256), 0, st, g));
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ SRM_OK, SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_HIP, SRM_E_RANK, SRM_E_NOTPD, \
 STATUS_NAMES = {0: "SRM_OK", 1: "SRM_E_ARG", 2: "SRM_E_WORKSPACE", 3: "SRM_E_HIP",
                 4: "SRM_E_RANK", 5: "SRM_E_NOTPD", 6: "SRM_E_NONFINITE", 7: "SRM_E_STATE"}
 PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2}
-SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE = 1, 2, 4, 8, 16
+SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE, SRM_GRAM = \
+    1, 2, 4, 8, 16, 32
 
 
 class SrmDesc(ctypes.Structure):
@@ -115,10 +116,12 @@ class SRM:
     place, anything else is uploaded (or, with stream_from_host, streamed
     through the library's staging area one subject at a time).  W0: list of
     N float64 host arrays (v_i x k, orthonormal columns); None draws random
-    orthonormal maps.  zscore standardises each voxel after demeaning."""
+    orthonormal maps.  zscore standardises each voxel after demeaning; gram
+    selects the sample-space iteration on G_i = Xhat_i^T Xhat_i."""
 
     def __init__(self, X, k: int, prec: str = "fp32", W0=None, flags: int = 0,
-                 seed: int = 0, stream_from_host: bool = False, zscore: bool = False):
+                 seed: int = 0, stream_from_host: bool = False, zscore: bool = False,
+                 gram: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise SRMError(SRM_E_HIP, "no HIP device visible")
@@ -127,6 +130,8 @@ class SRM:
         xs = []
         if zscore:
             flags |= SRM_ZSCORE
+        if gram:
+            flags |= SRM_GRAM
         if stream_from_host:
             flags |= SRM_X_HOST
             for x in X:
@@ -167,7 +172,7 @@ class SRM:
         _check(_lib.srm_fit(self._ctx, int(n_iter), ll.ctypes.data_as(_DP)))
         return ll[:n_iter]
 
-    PHASES = ("mphase", "ephase", "polar", "ereduce", "posterior", "fused")
+    PHASES = ("mphase", "ephase", "polar", "ereduce", "posterior", "fused", "gram")
 
     def profile(self, n_iter: int) -> dict:
         """Milliseconds per kernel phase summed over n_iter iterations, from HIP

@@ -35,14 +35,15 @@ def _say(*a):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,bar", [("fp32", 1e-4), ("bf16x2", 1e-3)])
-def test_plain16_full_size_against_complete_oracle(prec, bar):
+@pytest.mark.parametrize("prec,bar,gram", [("fp32", 1e-4, False), ("bf16x2", 1e-3, False),
+                                           ("fp32", 1e-4, True)])
+def test_plain16_full_size_against_complete_oracle(prec, bar, gram):
     srm = _srm()
     w = synth.WORKLOADS["plain16"]
     n_iter = 3
     d = synth.generate(w, seed=0)
-    _say(f"[case] plain16 full size prec={prec} iters={n_iter}")
-    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"])
+    _say(f"[case] plain16 full size prec={prec} gram={gram} iters={n_iter}")
+    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"], gram=gram)
     g.fit(n_iter)
     ora = oracle.em_fit(d["X"], w.k, n_iter, d["W0"], final_loglik=True)
     e = compare(g, ora, w.n_subjects)
@@ -53,14 +54,15 @@ def test_plain16_full_size_against_complete_oracle(prec, bar):
 
 
 @pytest.mark.timeout(900)
-def test_batch1024_full_size_sampled_m_step_and_properties():
+@pytest.mark.parametrize("gram", [False, True])
+def test_batch1024_full_size_sampled_m_step_and_properties(gram):
     import torch
     srm = _srm()
     w = synth.WORKLOADS["batch1024"]
     n_iter = 5
-    _say("[case] batch1024 full size: generating 1024 subjects on the device")
+    _say(f"[case] batch1024 full size gram={gram}: generating 1024 subjects on the device")
     X, W0, gl = synth.to_device(w, seed=0)
-    g = srm.SRM(X, w.k, prec="bf16x2", W0=W0, flags=srm.SRM_NO_W0_CHECK)
+    g = srm.SRM(X, w.k, prec="bf16x2", W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
     del X
     torch.cuda.empty_cache()
     g.fit(n_iter)
