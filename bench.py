@@ -81,12 +81,15 @@ def algorithmic(w, v, prec):
             "iter_flops": mph["flops"] + eph["flops"]}
 
 
-def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps):
+def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
     import torch
-    log(f"[bench] init {prec}")
-    t0 = time.time()
-    g = srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK)
-    log(f"[bench] init {prec} done in {time.time() - t0:.1f}s; warmup {warmup}")
+    log(f"[bench] init {prec}{' sample-space' if gram else ''}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
     if warmup:
         g.fit(warmup)
     torch.cuda.synchronize()
@@ -101,7 +104,11 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps):
     alg = algorithmic(w, v, prec)
     if ph.get("fused", 0.0) > 0.0:  # one-pass sweep: Xhat read once, A never stored
         alg["iter_bytes"] = alg["fused"]["bytes"]
-    res = {"iters_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+    if gram:  # per iteration: G_i (t x t FP64) read once, S G_i and S G_i S^T
+        Nn, t, k = float(len(v)), float(w.t), float(w.k)
+        alg["gram"] = {"bytes": Nn * t * t * 8, "flops": 2.0 * Nn * k * t * t + 2.0 * Nn * k * k * t}
+        alg["iter_bytes"], alg["iter_flops"] = alg["gram"]["bytes"], alg["gram"]["flops"]
+    res = {"iters_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "init_s": init_s,
            "hbm_GBps": alg["iter_bytes"] / (dt / steps) / 1e9,
            "phase_ms": ph, "alg": alg, "ll_last": float(ll[-1]) if len(ll) else None}
     return g, res
@@ -169,6 +176,8 @@ def main():
     ap.add_argument("--cpu-subjects", type=int, default=8)
     ap.add_argument("--subjects", type=int, default=0,
                     help="development only: fewer subjects of the same shape")
+    ap.add_argument("--no-gram", action="store_true",
+                    help="skip the sample-space (G_i = Xhat_i^T Xhat_i) variant")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GB: also run one plain device copy of this size "
                          "(calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -202,6 +211,13 @@ def main():
             check = sampled_check(g, w, args.seed, [int(s) for s in subs])
             log(f"[bench] sampled oracle check {check}")
         results[prec] = res
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    gram_res = None
+    if not args.no_gram:
+        g, gram_res = run_form(srm, X, W0, w, v, forms[0], args.steps, args.warmup,
+                               args.profile_steps, gram=True)
         g.close()
         del g
         torch.cuda.empty_cache()
@@ -245,6 +261,22 @@ def main():
             "hbm_GBps": r["hbm_GBps"], "phase_ms": r["phase_ms"],
             "mfma_TFLOPs": r["alg"]["iter_flops"] / (r["ms_per_step"] / 1e3) / 1e12}
         out[f"speedup_vs_{prec}"] = head["iters_per_s"] / r["iters_per_s"]
+    if gram_res is not None:
+        ga = gram_res["alg"]["gram"]
+        gms = gram_res["phase_ms"].get("gram", 0.0)
+        n_fit = w.n_iter
+        out["sample_space_variant"] = {
+            "note": "separate variant, not the headline: G_i = Xhat_i^T Xhat_i formed once "
+                    "in init, iterations read no voxel data",
+            "storage": forms[0], "iters_per_s": gram_res["iters_per_s"],
+            "ms_per_step": gram_res["ms_per_step"], "phase_ms": gram_res["phase_ms"],
+            "init_s": gram_res["init_s"], "streamed_init_s": head["init_s"],
+            "fit_s_at_workload_iters": {
+                "iters": n_fit,
+                "sample_space": gram_res["init_s"] + n_fit * gram_res["ms_per_step"] / 1e3,
+                "streamed": head["init_s"] + n_fit * head["ms_per_step"] / 1e3},
+            "k_gram_z_fp64_TFLOPs": ga["flops"] / (gms / 1e3) / 1e12 if gms > 0 else None,
+            "k_gram_z_GBps": ga["bytes"] / (gms / 1e3) / 1e9 if gms > 0 else None}
     if check is not None:
         out["error_vs_oracle"] = check
     if args.copy_probe > 0:

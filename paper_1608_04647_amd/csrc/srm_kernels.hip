@@ -536,7 +536,10 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
   __shared__ uint4 SLs[NSTEP][NB][64];
   __shared__ uint2 ARH[NRB][NB][64][2];  // [.][.][lane][row half]
   __shared__ uint2 ARL[NRB][NB][64][2];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // readfirstlane: the wave index (and every buffer descriptor built from it)
+  // is wave-uniform, so descriptors live in scalar registers.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const uint16_t* XH = (const uint16_t*)a.xh;
   const uint16_t* XL = (const uint16_t*)a.xl;

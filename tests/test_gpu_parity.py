@@ -67,6 +67,8 @@ CASES = {
     "k128": synth.Workload("k128", 2, 200, 260, 140, 128, 3, rho_lo=0.3, rho_hi=0.6),
     # single subject; smallest k
     "n1k1": synth.Workload("n1k1", 1, 40, 40, 16, 1, 5),
+    # 500 TRs and k = 50: the batched workload's shape per subject
+    "wide": synth.Workload("wide", 3, 200, 700, 500, 50, 4, sigma_lo=0.5, sigma_hi=2.0),
 }
 
 
@@ -88,7 +90,7 @@ def test_parity(case, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2", "bf16"])
-@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "n1k1"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "n1k1", "wide"])
 def test_sample_space_iteration_parity(case, prec):
     """The sample-space iteration (G_i = Xhat_i^T Xhat_i formed once, then
     S G_i and S G_i S^T per iteration) reaches the oracle's EM iterate."""
@@ -330,7 +332,7 @@ def test_getters_before_first_iteration():
     assert len(g.loglik()) == 1
 
 
-@pytest.mark.parametrize("case", ["tiny", "slices", "ragged"])
+@pytest.mark.parametrize("case", ["tiny", "slices", "ragged", "wide"])
 def test_fused_and_two_pass_sweeps_agree(case):
     """The one-pass sweep (A never stored) and the two-pass sweep (A = Xhat S^T
     written, then A^T Xhat) are the same EM; both meet the BF16 bar against the
