@@ -228,6 +228,8 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_xptr = take(sizeof(void*) * p.N);
   if (p.gram) {
     p.nq = (int)(p.ldt / 64);
+    if ((int64_t)p.nq * (p.nq + 1) / 2 * p.N >= ((int64_t)1 << 31))
+      return fail(SRM_E_ARG, "SRM_GRAM: too many Gram tiles (t or N too large)");
     p.o_G = take((size_t)p.N * p.ldt * p.ldt * 8);
     p.o_gz = take((size_t)p.N * p.nq * p.KP * p.KP * 8);
     p.o_subjg = take(sizeof(Subject) * p.N);

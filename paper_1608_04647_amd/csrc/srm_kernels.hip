@@ -1293,94 +1293,191 @@ __global__ __launch_bounds__(256) void k_map(MapArgs a) {
 // ---------------------------------------------------------------------------
 
 // G_i tile (64 x 64 TRs) for an upper tile pair (ta <= tb), mirrored below
-// the diagonal.  Contraction over the subject's rows with FP32 matrix cores,
-// 256-row chunks flushed into FP64 accumulators; the four waves take
-// interleaved 16-row steps and are summed in a fixed order.
-template <int PREC>
-__device__ __forceinline__ float x_at(const GBArgs& a, int64_t o) {
-  if constexpr (PREC == P_FP32) return ((const float*)a.xh)[o];
-  float v = bf2f(((const uint16_t*)a.xh)[o]);
-  if constexpr (PREC == P_BF16X2) v += bf2f(((const uint16_t*)a.xl)[o]);
-  return v;  // hi + lo is exact in FP32
-}
-
+// the diagonal; one workgroup per (subject, pair), the pairs of a subject
+// placed on one XCD so that its rows are fetched into that L2 once.  The
+// contraction over the subject's rows runs on matrix cores with FP32
+// accumulation over 16 row blocks per wave, flushed into FP64 accumulators;
+// the four waves take interleaved blocks and are summed in a fixed order.
+//  FP32 storage: 16x16x4 FP32 products, 16-row blocks;
+//  BF16 forms:   16x16x32 bf16 products on the stored planes (all four
+//                hi/lo products for hi + lo storage), 32-row blocks read as
+//                four TRs x eight rows per lane (the rows-as-K layout).
 template <int PREC>
 __global__ __launch_bounds__(256) void k_gram_build(GBArgs a) {
   __shared__ double L[64][65];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  int idx = blockIdx.x, ta = 0;
+  const int npairs = a.nt * (a.nt + 1) / 2;
+  const int h = xcd_remap(blockIdx.x, gridDim.x);
+  const int subj = h / npairs;
+  int idx = h % npairs, ta = 0;
   while (idx >= a.nt - ta) {
     idx -= a.nt - ta;
     ++ta;
   }
   const int tb = ta + idx;
-  const Subject su = a.subj[blockIdx.y];
+  const Subject su = a.subj[subj];
   const int64_t ca = 64 * (int64_t)ta, cb = 64 * (int64_t)tb;
+  const int ldt = (int)a.ldt;
   double acc64[4][4][4];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc64[mb][nb][e] = 0.0;
-  const int nstep = su.vp / 16;
-  for (int s0 = wave; s0 < nstep; s0 += 4 * 16) {
-    f32x4 acc[4][4];
+      for (int e = 0; e < 4; ++e) acc64[u][v][e] = 0.0;
+
+  if constexpr (PREC == P_FP32) {
+    // acc64[mb][nb][e] holds G[ca + 16 mb + 4 g + e][cb + 16 nb + n]
+    const float* X = (const float*)a.xh;
+    const int nstep = su.vp / 16;
+    for (int s0 = wave; s0 < nstep; s0 += 4 * 16) {
+      f32x4 acc[4][4];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int s1 = min(nstep, s0 + 4 * 16);
-    for (int st = s0; st < s1; st += 4) {
-      const int64_t r = su.row0 + 16 * (int64_t)st + 4 * g;
-      float xa[4][4], xb[4][4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) xa[mb][e] = x_at<PREC>(a, (r + e) * a.ldt + ca + 16 * mb + n);
-      if (ta != tb) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb)
-            xb[nb][e] = x_at<PREC>(a, (r + e) * a.ldt + cb + 16 * nb + n);
-      } else {
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int s1 = min(nstep, s0 + 4 * 16);
+      for (int st = s0; st < s1; st += 4) {
+        const int64_t r = su.row0 + 16 * (int64_t)st + 4 * g;
+        float xa[4][4], xb[4][4];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) xb[nb][e] = xa[nb][e];
+          for (int mb = 0; mb < 4; ++mb) xa[mb][e] = X[(r + e) * ldt + ca + 16 * mb + n];
+        if (ta != tb) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) xb[nb][e] = X[(r + e) * ldt + cb + 16 * nb + n];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) xb[nb][e] = xa[nb][e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+              acc[mb][nb] = mfma_f32(xa[mb][e], xb[nb][e], acc[mb][nb]);
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma_f32(xa[mb][e], xb[nb][e], acc[mb][nb]);
-    }
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc64[mb][nb][e] += (double)acc[mb][nb][e];
-  }
-  // Accumulator lane (n, g) element e holds G[ca + 16 mb + 4 g + e][cb + 16 nb + n].
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
+          for (int e = 0; e < 4; ++e) acc64[mb][nb][e] += (double)acc[mb][nb][e];
+    }
+  } else {
+    // Lane (n, g) loads, for rows 4 g + (e & 3) + 16 (e >> 2) of a 32-row
+    // block, the TRs 4 n .. 4 n + 3 of a tile; operand q (TR 4 n + q) then
+    // holds that column's eight rows.  acc64[qa][qb][r] holds
+    // G[ca + 16 g + 4 r + qa][cb + 4 n + qb].
+    constexpr bool X2 = PREC == P_BF16X2;
+    const uint16_t* XH = (const uint16_t*)a.xh;
+    const uint16_t* XL = (const uint16_t*)a.xl;
+    const int vo = (4 * g * ldt + 4 * n) * 2;
+    const bool diag = ta == tb;
+    const int nblk = su.vp / 32;
+    uint2 ra[2][2][8], rbv[2][2][8];  // [buffer][plane][e]
+    auto load = [&](int buf, int b) __attribute__((always_inline)) {
+      const int64_t r0 = su.row0 + 32 * (int64_t)b;
+      const auto AH = make_rsrc(XH + r0 * ldt + ca, 32u * ldt * 2u);
+      const auto AL = make_rsrc(XL + r0 * ldt + ca, 32u * ldt * 2u);
+      const auto BH = make_rsrc(XH + r0 * ldt + cb, 32u * ldt * 2u);
+      const auto BL = make_rsrc(XL + r0 * ldt + cb, 32u * ldt * 2u);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int so = ((e & 3) + 16 * (e >> 2)) * ldt * 2;
+        ra[buf][0][e] = bload8(AH, vo, so);
+        if constexpr (X2) ra[buf][1][e] = bload8(AL, vo, so);
+        if (!diag) {
+          rbv[buf][0][e] = bload8(BH, vo, so);
+          if constexpr (X2) rbv[buf][1][e] = bload8(BL, vo, so);
+        }
+      }
+    };
+    auto repack = [&](const uint2 (&x)[8], int q) __attribute__((always_inline)) {
+      uint4 o;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t a0 = (q < 2) ? x[2 * d].x : x[2 * d].y;
+        const uint32_t a1 = (q < 2) ? x[2 * d + 1].x : x[2 * d + 1].y;
+        ((uint32_t*)&o)[d] = (q & 1) ? ((a0 >> 16) | (a1 & 0xffff0000u))
+                                     : ((a0 & 0xffffu) | (a1 << 16));
+      }
+      return o;
+    };
+    f32x4 acc[4][4];
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+      uint4 Ah[4], Al[4], Bh[4], Bl[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Ah[q] = repack(ra[buf][0], q);
+        if constexpr (X2) Al[q] = repack(ra[buf][1], q);
+        if (!diag) {
+          Bh[q] = repack(rbv[buf][0], q);
+          if constexpr (X2) Bl[q] = repack(rbv[buf][1], q);
+        } else {
+          Bh[q] = Ah[q];
+          if constexpr (X2) Bl[q] = Al[q];
+        }
+      }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+          acc[qa][qb] = mfma_bf16(Ah[qa], Bh[qb], acc[qa][qb]);
+          if constexpr (X2) {
+            acc[qa][qb] = mfma_bf16(Ah[qa], Bl[qb], acc[qa][qb]);
+            acc[qa][qb] = mfma_bf16(Al[qa], Bh[qb], acc[qa][qb]);
+            acc[qa][qb] = mfma_bf16(Al[qa], Bl[qb], acc[qa][qb]);
+          }
+        }
+    };
+    for (int b0 = wave; b0 < nblk; b0 += 4 * 16) {
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int b1 = min(nblk, b0 + 4 * 16);
+      load(0, b0);
+      for (int b = b0; b < b1; b += 8) {
+        if (b + 4 < b1) load(1, b + 4);
+        compute(0);
+        if (b + 4 >= b1) break;
+        if (b + 8 < b1) load(0, b + 8);
+        compute(1);
+      }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[qa][qb][r] += (double)acc[qa][qb][r];
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
           for (int e = 0; e < 4; ++e) {
-            double& d = L[16 * mb + 4 * g + e][16 * nb + n];
-            d = (w == 0 ? 0.0 : d) + acc64[mb][nb][e];
+            const int pr = (PREC == P_FP32) ? 16 * u + 4 * g + e : 16 * g + 4 * e + u;
+            const int pc = (PREC == P_FP32) ? 16 * v + n : 4 * n + v;
+            double& d = L[pr][pc];
+            d = (w == 0 ? 0.0 : d) + acc64[u][v][e];
           }
     }
     __syncthreads();
   }
-  double* G = a.G + (int64_t)blockIdx.y * a.ldt * a.ldt;
+  double* G = a.G + (int64_t)subj * a.ldt * a.ldt;
   const int c = threadIdx.x & 63;
   for (int p = threadIdx.x >> 6; p < 64; p += 4) G[(ca + p) * a.ldt + cb + c] = L[p][c];
   if (ta != tb)
@@ -1388,24 +1485,30 @@ __global__ __launch_bounds__(256) void k_gram_build(GBArgs a) {
 }
 
 // Z_i[:, q-tile] = S G_i[:, q-tile] in FP64 (k x 64 per workgroup), stored in
-// the subject's E-phase partial, and the tile's share of Z_i S^T.
+// the subject's E-phase partial, and the tile's share of Z_i S^T.  Thread t
+// holds a (KP / 16) x 4 block: features t / 16 + 16 i, TRs 4 (t % 16) + m.
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
-  constexpr int NJ = KP / 4;
+  constexpr int NI = KP / 16;
   constexpr int PC = 32;  // TRs per staged chunk
   constexpr int SM1 = PC * 64 + KP * (PC + 1), SM2 = 2 * KP * 65;
   __shared__ double sm[SM1 > SM2 ? SM1 : SM2];
-  const int c = threadIdx.x & 63, jr = threadIdx.x >> 6;
+  const int cg = threadIdx.x & 15, rg = threadIdx.x >> 4;
   const int qt = blockIdx.x, i = blockIdx.y;
   const int64_t q0 = 64 * (int64_t)qt;
   const double* G = a.G + (int64_t)i * a.ldt * a.ldt;
-  double acc[NJ];
+  double acc[NI][4];
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) acc[u] = 0.0;
-  double (*Gs)[64] = reinterpret_cast<double (*)[64]>(sm);            // [PC][64]
+  for (int u = 0; u < NI; ++u)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[u][m] = 0.0;
+  double (*Gs)[64] = reinterpret_cast<double (*)[64]>(sm);                  // [PC][64]
   double (*Ss)[PC + 1] = reinterpret_cast<double (*)[PC + 1]>(sm + PC * 64);  // [KP][PC+1]
   for (int64_t p0 = 0; p0 < a.t; p0 += PC) {
-    for (int pp = jr; pp < PC; pp += 4) Gs[pp][c] = G[(p0 + pp) * a.ldt + q0 + c];
+    for (int idx = threadIdx.x; idx < PC * 64; idx += 256) {
+      const int pp = idx >> 6, c = idx & 63;
+      Gs[pp][c] = G[(p0 + pp) * a.ldt + q0 + c];
+    }
     for (int idx = threadIdx.x; idx < KP * PC; idx += 256) {
       const int j = idx / PC, pp = idx % PC;
       Ss[j][pp] = (j < a.k && p0 + pp < a.t) ? a.S[(int64_t)j * a.ldt + p0 + pp] : 0.0;
@@ -1413,22 +1516,34 @@ __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
     __syncthreads();
 #pragma unroll 4
     for (int pp = 0; pp < PC; ++pp) {
-      const double gv = Gs[pp][c];
+      double gv[4];
 #pragma unroll
-      for (int u = 0; u < NJ; ++u) acc[u] += Ss[jr + 4 * u][pp] * gv;
+      for (int m = 0; m < 4; ++m) gv[m] = Gs[pp][4 * cg + m];
+#pragma unroll
+      for (int u = 0; u < NI; ++u) {
+        const double sv = Ss[rg + 16 * u][pp];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[u][m] += sv * gv[m];
+      }
     }
     __syncthreads();
   }
   float* Z = a.zpart + (int64_t)i * KP * a.ldt;
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) Z[(int64_t)(jr + 4 * u) * a.ldt + q0 + c] = (float)acc[u];
+  for (int u = 0; u < NI; ++u)
+    *(float4*)(Z + (int64_t)(rg + 16 * u) * a.ldt + q0 + 4 * cg) =
+        make_float4((float)acc[u][0], (float)acc[u][1], (float)acc[u][2], (float)acc[u][3]);
   // Gram share: sum over this tile's 64 TRs of Z[j][q] S[l][q].
   double (*Zt)[65] = reinterpret_cast<double (*)[65]>(sm);
   double (*St)[65] = reinterpret_cast<double (*)[65]>(sm + KP * 65);
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) Zt[jr + 4 * u][c] = acc[u];
-  for (int l = jr; l < KP; l += 4)
+  for (int u = 0; u < NI; ++u)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Zt[rg + 16 * u][4 * cg + m] = acc[u][m];
+  for (int idx = threadIdx.x; idx < KP * 64; idx += 256) {
+    const int l = idx >> 6, c = idx & 63;
     St[l][c] = (l < a.k && q0 + c < a.t) ? a.S[(int64_t)l * a.ldt + q0 + c] : 0.0;
+  }
   __syncthreads();
   double* out = a.gz + ((int64_t)i * a.nq + qt) * KP * KP;
   for (int idx = threadIdx.x; idx < KP * KP; idx += 256) {
@@ -1572,7 +1687,8 @@ hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
 }
 
 hipError_t launch_gram_build(hipStream_t st, int prec, int npairs, int N, const GBArgs& a) {
-  SRM_PREC_SWITCH(prec, hipLaunchKernelGGL((k_gram_build<PR>), dim3(npairs, N), dim3(256), 0,
+  const int grid = npairs * N;  // bounded by the planner
+  SRM_PREC_SWITCH(prec, hipLaunchKernelGGL((k_gram_build<PR>), dim3(grid), dim3(256), 0,
                                            st, a));
   return hipGetLastError();
 }
