@@ -84,11 +84,11 @@ def algorithmic(w, v, prec):
 def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
     import torch
     log(f"[bench] init {prec}{' sample-space' if gram else ''}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     g = srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
-    torch.cuda.synchronize()
-    init_s = time.perf_counter() - t0
+    # the library's own initialisation (W0 upload, conversion, G_i for the
+    # sample-space variant, first E-step); the caller's workspace allocation
+    # is not part of it
+    init_s = g.init_seconds
     log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
     if warmup:
         g.fit(warmup)

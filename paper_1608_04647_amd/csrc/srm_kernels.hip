@@ -1017,13 +1017,14 @@ __global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
 template <int KP>
 __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
-  // Warm start keeps G, V and a product buffer in LDS (K padding <= 80);
-  // larger K keeps G and V in LDS (<= 96) or in global scratch, cold start.
+  // G and V live in LDS for K padding <= 96 (two workgroups per CU up to
+  // 80), in global scratch above; warm start up to 80 (its product passes
+  // go through registers).
   constexpr bool WARM = KP <= 80;
   constexpr bool IN_LDS = KP <= 96;
-  constexpr int NBUF = WARM ? 3 : 2;
   constexpr int MAXP = (KP + 1) / 2;
-  __shared__ double lds[IN_LDS ? NBUF * KP * LD : 1];
+  constexpr int NE = (KP * KP + 255) / 256;  // product entries per thread
+  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
@@ -1047,26 +1048,46 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   }
   const bool warm = WARM && a.sc->polar_warm != 0;
   if constexpr (WARM) {
-    double* T = V + KP * LD;
     const double* Vp = a.vprev + (int64_t)i * KP * KP;
     for (int idx = tid; idx < m * m; idx += 256) {
       const int p = idx / m, q = idx % m;
       V[p * LD + q] = warm ? Vp[p * KP + q] : (p == q && p < k ? 1.0 : 0.0);
     }
     __syncthreads();
-    if (warm) {  // G <- V^T G V, then rotate further from V
-      for (int idx = tid; idx < k * k; idx += 256) {
-        const int p = idx / k, q = idx % k;
+    if (warm) {  // G <- V^T (G V), then rotate further from V
+      double tv[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int idx = tid + 256 * u;
         double s = 0.0;
-        for (int r = 0; r < k; ++r) s += G[p * LD + r] * V[r * LD + q];
-        T[p * LD + q] = s;
+        if (idx < k * k) {
+          const int p = idx / k, q = idx % k;
+          for (int r = 0; r < k; ++r) s += G[p * LD + r] * V[r * LD + q];
+        }
+        tv[u] = s;
       }
       __syncthreads();
-      for (int idx = tid; idx < k * k; idx += 256) {
-        const int p = idx / k, q = idx % k;
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int idx = tid + 256 * u;
+        if (idx < k * k) G[(idx / k) * LD + idx % k] = tv[u];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int idx = tid + 256 * u;
         double s = 0.0;
-        for (int r = 0; r < k; ++r) s += V[r * LD + p] * T[r * LD + q];
-        G[p * LD + q] = s;
+        if (idx < k * k) {
+          const int p = idx / k, q = idx % k;
+          for (int r = 0; r < k; ++r) s += V[r * LD + p] * G[r * LD + q];
+        }
+        tv[u] = s;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int idx = tid + 256 * u;
+        if (idx < k * k) G[(idx / k) * LD + idx % k] = tv[u];
       }
     }
   } else {

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -161,8 +162,11 @@ class SRM:
         wptr = (_P * self.N)(*[w.ctypes.data for w in w0])
         torch.cuda.synchronize()
         ctx = _P()
+        t0 = time.perf_counter()
         _check(_lib.srm_init(ctypes.byref(ctx), ctypes.byref(self._desc), xptr, wptr,
                              _P(self._ws.data_ptr()), self.workspace_bytes))
+        # srm_init returns after its device work (it reads the device status)
+        self.init_seconds = time.perf_counter() - t0
         self._ctx = ctx
         self._dev = dev
 
