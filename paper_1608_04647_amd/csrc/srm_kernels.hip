@@ -501,17 +501,17 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
 
 // ---------------------------------------------------------------------------
 // One-pass sweep (BF16 forms, K padding <= 64, ldt in {128, 256, 384, 512}):
-// Xhat is read from HBM once per iteration.  Workgroup = NW = ldt / 64 waves
-// with all of S (bf16 hi+lo records) resident in LDS for the whole launch.
-// Each slice is walked in chunks of CH = 16 NW rows:
-//   part 1: each wave forms a 16-row block of A = Xhat S^T (all of its
-//           features, or one half) over all TRs; its Xhat rows stream from
-//           HBM through an 8-deep register ring,
-//           S operands come from LDS; the bf16 hi+lo result is written into
-//           the chunk's A records in LDS;
+// A = Xhat S^T never goes to HBM.  Workgroup = NW = ldt / 64 waves with all
+// of S (bf16 hi+lo records) resident in LDS for the whole launch.  Each
+// slice is walked in chunks of CH rows (16 NW; 64 with eight waves):
+//   part 1: wave w < CH / 16 forms the 16-row block w of A over all TRs,
+//           all features; its Xhat rows stream from HBM through a 4-deep
+//           register ring, S operands come from LDS one step ahead; the
+//           bf16 hi+lo result is written into the chunk's A records in LDS;
 //   part 2: after one barrier, wave w adds A^T Xhat[:, 64 w .. 64 w + 63]
-//           over the chunk into its Z columns (the chunk's Xhat is re-read
-//           while cache resident) and its share of the Gram tiles A^T A.
+//           over the chunk into its Z columns (reading the chunk's Xhat a
+//           second time, from the caches where it is still resident) and
+//           its share of the Gram tiles A^T A.
 // Z_s and G_s per slice equal what the two-pass E-phase forms from
 // A = Xhat S^T; A itself never goes to HBM.
 // ---------------------------------------------------------------------------
@@ -525,12 +525,13 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
   constexpr int NG = (NPAIR + NW - 1) / NW;
   constexpr int LDT = 64 * NW;
   constexpr int NSTEP = LDT / 32;  // 32-TR MFMA steps
-  // Part 1 may split the features of a 16-row block over NJP waves (smaller
-  // chunks); one part per wave measured fastest.
-  constexpr int NJP = 1;
-  constexpr int CH = 16 * NW / NJP;
+  // Chunk rows: one 16-row block per wave, except with eight waves, where
+  // half of them form A over 64-row chunks.  The smaller chunk keeps the
+  // lines that part 2 reads again within reach of the L2 (measured faster
+  // than splitting the features of a block over two waves).
+  constexpr int CH = (NW == 8) ? 8 * NW : 16 * NW;
+  constexpr int NPW = CH / 16;     // waves with part-1 work
   constexpr int NRB = CH / 32;     // A records (32-row blocks) per chunk
-  constexpr int NBP = NB / NJP;    // feature blocks per part-1 wave
   constexpr int D = 4;             // Xhat prefetch depth in part 1
   __shared__ uint4 SHs[NSTEP][NB][64];
   __shared__ uint4 SLs[NSTEP][NB][64];
@@ -567,16 +568,16 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
     for (int cr = 0; cr < sc.nrows; cr += CH) {
       const int nrow = min(CH, sc.nrows - cr);  // multiple of 32
       const int64_t rc = sc.row0 + cr;
-      // ---- part 1: rows [16 rw, 16 rw + 16), feature blocks of part jp
-      const int rw = wave % (CH / 16), jp = wave / (CH / 16);
-      if (16 * rw < nrow) {
+      // ---- part 1: rows [16 rw, 16 rw + 16), all feature blocks
+      const int rw = wave;
+      if (wave < NPW && 16 * rw < nrow) {
         const uint32_t wbytes = 16u * LDT * 2u;
         const auto RH = make_rsrc(XH + (rc + 16 * rw) * LDT, wbytes);
         const auto RL = make_rsrc(XL + (rc + 16 * rw) * LDT, wbytes);
         const int vx = (n * LDT + 8 * g) * 2;
-        f32x4 acc[NBP];
+        f32x4 acc[NB];
 #pragma unroll
-        for (int jb = 0; jb < NBP; ++jb) acc[jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int jb = 0; jb < NB; ++jb) acc[jb] = f32x4{0.f, 0.f, 0.f, 0.f};
         uint4 xh[D], xl[D];
 #pragma unroll
         for (int st = 0; st < D && st < NSTEP; ++st) {
@@ -585,20 +586,20 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
         }
         // S operands are read from LDS one step ahead (double buffer) so
         // their latency hides behind the previous step's products.
-        uint4 th[2][NBP], tl[2][NBP];
+        uint4 th[2][NB], tl[2][NB];
 #pragma unroll
-        for (int jj = 0; jj < NBP; ++jj) {
-          th[0][jj] = SHs[0][jp * NBP + jj][lane];
-          tl[0][jj] = SLs[0][jp * NBP + jj][lane];
+        for (int jj = 0; jj < NB; ++jj) {
+          th[0][jj] = SHs[0][jj][lane];
+          tl[0][jj] = SLs[0][jj][lane];
         }
 #pragma unroll
         for (int tb = 0; tb < NSTEP; ++tb) {
           const int st = tb % D, sb2 = tb & 1;
           if (tb + 1 < NSTEP) {
 #pragma unroll
-            for (int jj = 0; jj < NBP; ++jj) {
-              th[sb2 ^ 1][jj] = SHs[tb + 1][jp * NBP + jj][lane];
-              tl[sb2 ^ 1][jj] = SLs[tb + 1][jp * NBP + jj][lane];
+            for (int jj = 0; jj < NB; ++jj) {
+              th[sb2 ^ 1][jj] = SHs[tb + 1][jj][lane];
+              tl[sb2 ^ 1][jj] = SLs[tb + 1][jj][lane];
             }
           }
           const uint4 xa = xh[st];
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
           }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int jj = 0; jj < NBP; ++jj) {
+          for (int jj = 0; jj < NB; ++jj) {
             acc[jj] = mfma_bf16(xa, th[sb2][jj], acc[jj]);
             acc[jj] = mfma_bf16(xa, tl[sb2][jj], acc[jj]);
             if constexpr (X2) acc[jj] = mfma_bf16(xb, th[sb2][jj], acc[jj]);
@@ -619,13 +620,12 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
         }
         // lane holds A[16 rw + 4 g + i][16 jb + n]: half of an A record
 #pragma unroll
-        for (int jj = 0; jj < NBP; ++jj) {
-          const int jb = jp * NBP + jj;
+        for (int jb = 0; jb < NB; ++jb) {
           uint32_t h[4], l[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            h[i] = f2bf(acc[jj][i]);
-            l[i] = f2bf(acc[jj][i] - bf2f(h[i]));
+            h[i] = f2bf(acc[jb][i]);
+            l[i] = f2bf(acc[jb][i] - bf2f(h[i]));
           }
           ARH[rw >> 1][jb][lane][rw & 1] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
           ARL[rw >> 1][jb][lane][rw & 1] = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
