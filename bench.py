@@ -36,15 +36,24 @@ def log(*a):
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_04647_amd", "csrc", "srm_kernels.hip")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str) -> str:
+    """SHA-256 (16 hex digits) of one kernel's own source text: from its
+    template line (or __global__ line) to its closing brace."""
     import hashlib
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    import re
+    src = open(KERNEL_SRC).read()
+    m = (re.search(r"^template <[^\n]*>\n__global__[^\n]*\b" + kernel + r"\(", src, re.M) or
+         re.search(r"^__global__[^\n]*\b" + kernel + r"\(", src, re.M))
+    if m is None:
+        return "absent"
+    end = src.index("\n}\n", m.start()) + 3
+    return hashlib.sha256(src[m.start():end].encode()).hexdigest()[:16]
 
 
 def committed_traffic(kernel: str, workload: str, prec: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/<kernel>_<workload>_<prec>_traffic.md), or None when absent or
-    taken on a different kernel source."""
+    taken on a different source of that kernel."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -54,7 +63,7 @@ def committed_traffic(kernel: str, workload: str, prec: str):
             for kv in line.split(":", 1)[1].split():
                 k_, v_ = kv.split("=")
                 vals[k_] = v_
-    if vals.get("source_sha256_16") != kernel_source_hash():
+    if vals.get("source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals["bytes_per_launch"])
