@@ -32,7 +32,8 @@ Readings of the paper used here (the paper is silent, ambiguous or garbled):
       the inversion lemma (Eq. 7) and Eq. 8 -- see ``loglik``.
   R10 a rank-deficient A_i (lambda_min(A^T A) <= 1e-13 lambda_max) is an error.
   R11 inversions by Cholesky (Sec. II-C); a failure is an error.
-  R12 the data standardisation (z-score) named among the implementation's
+  (R12 and R13 concern the device's storage format and polar method only.)
+  R14 the data standardisation (z-score) named among the implementation's
       native helpers (Sec. IV-A) is taken per voxel over the samples, with the
       population standard deviation (1/t); a constant voxel (standard
       deviation 0) is only demeaned.  For float32 input the FP64 mean of a
@@ -84,7 +85,7 @@ def demean(X: np.ndarray):
 
 
 def zscore(X: np.ndarray):
-    """Per-voxel standardisation of Sec. IV-A (R12): (x - mu) / sd with sd the
+    """Per-voxel standardisation of Sec. IV-A (R14): (x - mu) / sd with sd the
     population standard deviation over the samples.
 
     Returns (mu [v], Z [v x t] float64, scale [v] = 1/sd, or 1 for a constant

@@ -225,7 +225,7 @@ def test_map_matches_oracle(prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
 def test_zscore_matches_oracle(prec):
-    """Standardised input (Sec. IV-A, reading R12): voxels given very different
+    """Standardised input (Sec. IV-A, reading R14): voxels given very different
     scales and offsets, one constant voxel; the fit, the stored mean and scale
     and the projection of held-out samples follow the oracle on Z."""
     srm = _srm()

@@ -279,7 +279,7 @@ def test_flop_model_counts():
 
 
 def test_p12_zscore_matches_scipy_and_standardises():
-    """Sec. IV-A data standardisation (reading R12) against scipy.stats.zscore
+    """Sec. IV-A data standardisation (reading R14) against scipy.stats.zscore
     (population standard deviation), with the per-voxel invariants it fixes."""
     from scipy import stats
     rng = np.random.default_rng(11)
