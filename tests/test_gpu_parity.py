@@ -69,6 +69,12 @@ CASES = {
     "n1k1": synth.Workload("n1k1", 1, 40, 40, 16, 1, 5),
     # 500 TRs and k = 50: the batched workload's shape per subject
     "wide": synth.Workload("wide", 3, 200, 700, 500, 50, 4, sigma_lo=0.5, sigma_hi=2.0),
+    # degenerate shapes: square maps (v_i = k), and the smallest problem
+    # (t = 2, one voxel, k = 1)
+    "vk": synth.Workload("vk", 3, 6, 6, 40, 6, 5),
+    "min": synth.Workload("min", 2, 1, 2, 2, 1, 4),
+    # the largest t the boundary accepts
+    "tmax": synth.Workload("tmax", 2, 30, 50, 65536, 3, 3),
 }
 
 
@@ -90,7 +96,8 @@ def test_parity(case, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2", "bf16"])
-@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "n1k1", "wide"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "n1k1", "wide",
+                                  "vk", "min"])
 def test_sample_space_iteration_parity(case, prec):
     """The sample-space iteration (G_i = Xhat_i^T Xhat_i formed once, then
     S G_i and S G_i S^T per iteration) reaches the oracle's EM iterate."""
