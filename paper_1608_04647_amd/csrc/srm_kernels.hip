@@ -1014,8 +1014,8 @@ __global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
 // rho_i^2 = (c_i - 2 tr(W_i^T A_i) + t tau) / (t v_i).
 // ---------------------------------------------------------------------------
 
-template <int KP>
-__global__ __launch_bounds__(256) void k_polar(QArgs a) {
+template <int KP, int NT>
+__global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
   // G and V live in LDS for K padding <= 96 (two workgroups per CU up to
   // 80), in global scratch above; warm start up to 80 (its product passes
@@ -1023,11 +1023,12 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   constexpr bool WARM = KP <= 80;
   constexpr bool IN_LDS = KP <= 96;
   constexpr int MAXP = (KP + 1) / 2;
-  constexpr int NE = (KP * KP + 255) / 256;  // product entries per thread
+  constexpr int NE = (KP * KP + NT - 1) / NT;  // product entries per thread
   __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
+  __shared__ double isq[KP];  // lambda_j^-1/2
   const int i = blockIdx.x, tid = threadIdx.x, k = a.k;
   double* G = IN_LDS ? lds : a.work + (int64_t)i * 2 * KP * LD;
   double* V = G + KP * LD;
@@ -1036,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   const int npair = m / 2;
 
   // G_i from the slices' upper 16x16 tiles, mirrored; dummy row/col zero.
-  for (int idx = tid; idx < m * m; idx += 256) {
+  for (int idx = tid; idx < m * m; idx += NT) {
     const int p = idx / m, q = idx % m;
     double s = 0.0;
     if (p < k && q < k) {
@@ -1049,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   const bool warm = WARM && a.sc->polar_warm != 0;
   if constexpr (WARM) {
     const double* Vp = a.vprev + (int64_t)i * KP * KP;
-    for (int idx = tid; idx < m * m; idx += 256) {
+    for (int idx = tid; idx < m * m; idx += NT) {
       const int p = idx / m, q = idx % m;
       V[p * LD + q] = warm ? Vp[p * KP + q] : (p == q && p < k ? 1.0 : 0.0);
     }
@@ -1058,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
       double tv[NE];
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
-        const int idx = tid + 256 * u;
+        const int idx = tid + NT * u;
         double s = 0.0;
         if (idx < k * k) {
           const int p = idx / k, q = idx % k;
@@ -1069,13 +1070,13 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
-        const int idx = tid + 256 * u;
+        const int idx = tid + NT * u;
         if (idx < k * k) G[(idx / k) * LD + idx % k] = tv[u];
       }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
-        const int idx = tid + 256 * u;
+        const int idx = tid + NT * u;
         double s = 0.0;
         if (idx < k * k) {
           const int p = idx / k, q = idx % k;
@@ -1086,12 +1087,12 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NE; ++u) {
-        const int idx = tid + 256 * u;
+        const int idx = tid + NT * u;
         if (idx < k * k) G[(idx / k) * LD + idx % k] = tv[u];
       }
     }
   } else {
-    for (int idx = tid; idx < m * m; idx += 256) {
+    for (int idx = tid; idx < m * m; idx += NT) {
       const int p = idx / m, q = idx % m;
       V[p * LD + q] = (p == q && p < k) ? 1.0 : 0.0;
     }
@@ -1102,8 +1103,20 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   // act on disjoint index pairs, so G <- J^T G J splits into independent
   // 2x2 blocks B_xy <- J_x^T B_xy J_y, and V <- V J into row pairs.
   for (int sweep = 0; sweep < 40; ++sweep) {
+    // A sweep in which no pair passes the rotation test changes nothing:
+    // test all pairs at once and stop before such a sweep.
     if (tid == 0) rotated = 0;
     __syncthreads();
+    for (int idx = tid; idx < m * m; idx += NT) {
+      const int p = idx / m, q = idx % m;
+      if (p < q && q < k) {
+        const double apq = G[p * LD + q];
+        if (fabs(apq) > 1e-15 * sqrt(fabs(G[p * LD + p] * G[q * LD + q])) && apq != 0.0)
+          rotated = 1;
+      }
+    }
+    __syncthreads();
+    if (!rotated) break;
     for (int rnd = 0; rnd < m - 1; ++rnd) {
       if (tid < npair) {
         int p, q;
@@ -1125,7 +1138,6 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
                               (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
-            rotated = 1;
           }
         }
         cs_[tid] = c;
@@ -1134,7 +1146,7 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
         qq_[tid] = q;
       }
       __syncthreads();
-      for (int idx = tid; idx < npair * npair; idx += 256) {
+      for (int idx = tid; idx < npair * npair; idx += NT) {
         const int x = idx / npair, y = idx % npair;
         const int p = pp_[x], q = qq_[x], r = pp_[y], t = qq_[y];
         const double cx = cs_[x], sx = sn_[x], cy = cs_[y], sy = sn_[y];
@@ -1147,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
         G[q * LD + r] = cy * m10 - sy * m11;
         G[q * LD + t] = sy * m10 + cy * m11;
       }
-      for (int idx = tid; idx < npair * m; idx += 256) {
+      for (int idx = tid; idx < npair * m; idx += NT) {
         const int x = idx / m, j = idx % m;
         const int p = pp_[x], q = qq_[x];
         const double c = cs_[x], s = sn_[x];
@@ -1157,8 +1169,6 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
       }
       __syncthreads();
     }
-    if (!rotated) break;
-    __syncthreads();
   }
 
   // Eigenvalues; rank check; sum of singular values of A_i.
@@ -1170,20 +1180,21 @@ __global__ __launch_bounds__(256) void k_polar(QArgs a) {
   }
   const bool rank_ok = lmin > 1e-13 * lmax && lmax > 0.0;
   for (int j = 0; j < k; ++j) ssq += sqrt(fmax(G[j * LD + j], 0.0));
+  for (int j = tid; j < k; j += NT) isq[j] = rank_ok ? 1.0 / sqrt(G[j * LD + j]) : 0.0;
+  __syncthreads();
   // P = V diag(lambda^-1/2) V^T  (written zero padded to KP x KP)
   double* P = a.P64 + (int64_t)i * KP * KP;
-  for (int idx = tid; idx < KP * KP; idx += 256) {
+  for (int idx = tid; idx < KP * KP; idx += NT) {
     const int p = idx / KP, q = idx % KP;
     double s = 0.0;
     if (p < k && q < k && rank_ok) {
-      for (int j = 0; j < k; ++j)
-        s += V[p * LD + j] * V[q * LD + j] / sqrt(G[j * LD + j]);
+      for (int j = 0; j < k; ++j) s += V[p * LD + j] * V[q * LD + j] * isq[j];
     }
     P[idx] = s;
   }
   if constexpr (WARM) {
     double* Vp = a.vprev + (int64_t)i * KP * KP;
-    for (int idx = tid; idx < m * m; idx += 256) {
+    for (int idx = tid; idx < m * m; idx += NT) {
       const int p = idx / m, q = idx % m;
       Vp[p * KP + q] = V[p * LD + q];
     }
@@ -1665,7 +1676,8 @@ hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
   return hipGetLastError();
 }
 hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
-  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_polar<KP>), dim3(N), dim3(256), 0, st, a));
+  // Four waves per subject (one wave per subject measured 2x slower).
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_polar<KP, 256>), dim3(N), dim3(256), 0, st, a));
   hipLaunchKernelGGL(k_polar_done, dim3(1), dim3(64), 0, st, a.sc);
   return hipGetLastError();
 }
