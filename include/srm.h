@@ -89,8 +89,9 @@ enum {
                            per-voxel scale.                                    */
   SRM_GRAM = 32u        /* sample-space iteration (the Discussion's change of
                            complexity from voxels to samples): srm_init forms
-                           G_i = Xhat_i^T Xhat_i (t x t, FP64, N t^2 8 bytes of
-                           workspace) in one pass over the data; each iteration
+                           G_i = Xhat_i^T Xhat_i (t x t; FP32 for the BF16
+                           forms, FP64 for SRM_FP32 storage: N t^2 4 or 8 bytes
+                           of workspace) in one pass over the data; each iteration
                            then uses A_i^T Xhat_i = S G_i and A_i^T A_i =
                            S G_i S^T and reads no voxel data.  The same EM
                            iterate as the streamed sweep up to rounding; pays

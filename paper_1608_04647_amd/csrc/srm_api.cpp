@@ -230,7 +230,8 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
     p.nq = (int)(p.ldt / 64);
     if ((int64_t)p.nq * (p.nq + 1) / 2 * p.N >= ((int64_t)1 << 31))
       return fail(SRM_E_ARG, "SRM_GRAM: too many Gram tiles (t or N too large)");
-    p.o_G = take((size_t)p.N * p.ldt * p.ldt * 8);
+    // FP32 storage keeps G_i in FP64 (and runs its products in FP64).
+    p.o_G = take((size_t)p.N * p.ldt * p.ldt * (p.prec == SRM_FP32 ? 8 : 4));
     p.o_gz = take((size_t)p.N * p.nq * p.KP * p.KP * 8);
     p.o_subjg = take(sizeof(Subject) * p.N);
   }
@@ -476,7 +477,9 @@ hipError_t enqueue_iteration(srm_ctx* c) {
               (int64_t)p.KP * p.ldt, (int64_t)(p.srec_bytes / 16), p.KP * p.KP};
   if ((e = launch_copy_state(st, ca)) != hipSuccess) return e;
   if (p.gram) {
-    GZArgs za{c->at<double>(p.o_G), c->at<double>(p.o_s64cur), c->at<float>(p.o_zpart),
+    const bool g64 = p.prec == SRM_FP32;
+    GZArgs za{g64 ? nullptr : c->at<float>(p.o_G), g64 ? c->at<double>(p.o_G) : nullptr,
+              c->at<double>(p.o_s64cur), c->at<float>(p.o_zpart),
               c->at<double>(p.o_gz), p.t, p.ldt, p.nq, p.k};
     GSArgs ga{c->at<double>(p.o_gz), c->at<float>(p.o_gpart), p.nq};
     {
@@ -765,7 +768,9 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
     if (up(P.o_subjg, sg.data(), sizeof(Subject) * P.N) != hipSuccess)
       return bail(fail(SRM_E_HIP, "upload of tables failed"));
     const int nt = (int)(P.ldt / 64);
-    GBArgs gb{q.xh, q.xl, c->at<Subject>(P.o_subj), c->at<double>(P.o_G), P.ldt, nt};
+    const bool g64 = P.prec == SRM_FP32;
+    GBArgs gb{q.xh, q.xl, c->at<Subject>(P.o_subj), g64 ? nullptr : c->at<float>(P.o_G),
+              g64 ? c->at<double>(P.o_G) : nullptr, P.ldt, nt};
     if (launch_gram_build(c->stream, P.prec, nt * (nt + 1) / 2, P.N, gb) != hipSuccess)
       return bail(fail(SRM_E_HIP, "Gram launch failed"));
   }

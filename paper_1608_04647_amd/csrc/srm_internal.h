@@ -240,7 +240,8 @@ struct GBArgs {
   const void* xh;
   const void* xl;
   const Subject* subj;
-  double* G;        // [N][ldt][ldt]
+  float* G;         // [N][ldt][ldt] FP32 (BF16 forms), or null
+  double* G64;      // [N][ldt][ldt] FP64 (FP32 storage), or null
   int64_t ldt;
   int32_t nt;       // ldt / 64 column tiles
 };
@@ -248,7 +249,8 @@ struct GBArgs {
 // Per iteration: Z_i = S G_i (into the subject's E-phase partial) and the
 // per-column-tile partials of Z_i S^T.
 struct GZArgs {
-  const double* G;
+  const float* G;     // FP32 G_i (BF16 forms), or null
+  const double* G64;  // FP64 G_i (FP32 storage), or null
   const double* S;  // [KP][ldt] FP64 S of the current posterior
   float* zpart;     // [N][KP][ldt]
   double* gz;       // [N][nq][KP][KP]

@@ -1509,18 +1509,107 @@ __global__ __launch_bounds__(256) void k_gram_build(GBArgs a) {
     }
     __syncthreads();
   }
-  double* G = a.G + (int64_t)subj * a.ldt * a.ldt;
+  const int64_t gbase = (int64_t)subj * a.ldt * a.ldt;
   const int c = threadIdx.x & 63;
-  for (int p = threadIdx.x >> 6; p < 64; p += 4) G[(ca + p) * a.ldt + cb + c] = L[p][c];
+  auto put = [&](int64_t o, double v) {
+    if (a.G64) a.G64[gbase + o] = v;
+    else a.G[gbase + o] = (float)v;
+  };
+  for (int p = threadIdx.x >> 6; p < 64; p += 4) put((ca + p) * a.ldt + cb + c, L[p][c]);
   if (ta != tb)
-    for (int p = threadIdx.x >> 6; p < 64; p += 4) G[(cb + p) * a.ldt + ca + c] = L[c][p];
+    for (int p = threadIdx.x >> 6; p < 64; p += 4) put((cb + p) * a.ldt + ca + c, L[c][p]);
 }
 
-// Z_i[:, q-tile] = S G_i[:, q-tile] in FP64 (k x 64 per workgroup), stored in
-// the subject's E-phase partial, and the tile's share of Z_i S^T.  Thread t
-// holds a (KP / 16) x 4 block: features t / 16 + 16 i, TRs 4 (t % 16) + m.
+// BF16 forms: Z_i[:, q-tile] = S G_i[:, q-tile] for one 64-TR tile (FP32
+// matrix cores, FP32 G_i, S from the FP64 posterior rounded to FP32), stored
+// in the subject's E-phase partial, and the tile's share of Z_i S^T (FP32
+// products, FP64 out).
+// Wave w owns TRs q0 + 16 w .. + 15 of the tile for all features.
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
+  constexpr int NB = KP / 16;
+  constexpr int PC = 64;        // TRs per staged S chunk
+  constexpr int LS = PC + 4;    // padded row of the staged chunk
+  __shared__ float Ss[KP][LS];  // S[:, p0 .. p0 + 63], later S[:, q-tile]
+  __shared__ float Zt[KP][LS];  // the Z tile
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int qt = blockIdx.x, i = blockIdx.y;
+  const int64_t q0 = 64 * (int64_t)qt;
+  const float* G = a.G + (int64_t)i * a.ldt * a.ldt + q0 + 16 * wave + n;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) acc[jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t p0 = 0; p0 < a.t; p0 += PC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < KP * PC; idx += 256) {
+      const int j = idx / PC, pp = idx % PC;
+      Ss[j][pp] = (j < a.k && p0 + pp < a.t) ? (float)a.S[(int64_t)j * a.ldt + p0 + pp] : 0.f;
+    }
+    __syncthreads();
+    // K-step of 16 TRs: lane group g takes TRs 4 g .. 4 g + 3 (one per
+    // product), for both operands alike.
+#pragma unroll 2
+    for (int ps = 0; ps < PC; ps += 16) {
+      float gv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t p = p0 + ps + 4 * g + e;  // < ldt: chunks end at ldt
+        gv[e] = G[p * a.ldt];
+      }
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        const float4 sv = *(const float4*)&Ss[16 * jb + n][ps + 4 * g];
+        acc[jb] = mfma_f32(sv.x, gv[0], acc[jb]);
+        acc[jb] = mfma_f32(sv.y, gv[1], acc[jb]);
+        acc[jb] = mfma_f32(sv.z, gv[2], acc[jb]);
+        acc[jb] = mfma_f32(sv.w, gv[3], acc[jb]);
+      }
+    }
+  }
+  // lane holds Z[16 jb + 4 g + r][q0 + 16 wave + n]
+  float* Z = a.zpart + (int64_t)i * KP * a.ldt + q0 + 16 * wave + n;
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Z[(int64_t)(16 * jb + 4 * g + r) * a.ldt] = acc[jb][r];
+      Zt[16 * jb + 4 * g + r][16 * wave + n] = acc[jb][r];
+    }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < KP * 64; idx += 256) {
+    const int l = idx >> 6, c = idx & 63;
+    Ss[l][c] = (l < a.k && q0 + c < a.t) ? (float)a.S[(int64_t)l * a.ldt + q0 + c] : 0.f;
+  }
+  __syncthreads();
+  // Gram share over the tile's 64 TRs: block (j1, j2) of Z S^T, blocks
+  // dealt round-robin to the waves; K-permuted as above.
+  double* out = a.gz + ((int64_t)i * a.nq + qt) * KP * KP;
+  for (int blk = wave; blk < NB * NB; blk += 4) {
+    const int j1 = blk / NB, j2 = blk % NB;
+    f32x4 c4 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ps = 0; ps < 64; ps += 16) {
+      const float4 zv = *(const float4*)&Zt[16 * j1 + n][ps + 4 * g];
+      const float4 sv = *(const float4*)&Ss[16 * j2 + n][ps + 4 * g];
+      c4 = mfma_f32(zv.x, sv.x, c4);
+      c4 = mfma_f32(zv.y, sv.y, c4);
+      c4 = mfma_f32(zv.z, sv.z, c4);
+      c4 = mfma_f32(zv.w, sv.w, c4);
+    }
+    // lane holds share[16 j1 + 4 g + r][16 j2 + n]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(16 * j1 + 4 * g + r) * KP + 16 * j2 + n] = (double)c4[r];
+  }
+}
+
+// FP32 storage: the same products from an FP64 G_i, in FP64 throughout (the
+// polar factor is then as consistent with A = Xhat S^T as in the streamed
+// sweep).  Thread t holds a (KP / 16) x 4 block: features t / 16 + 16 i,
+// TRs 4 (t % 16) + m.
+template <int KP>
+__global__ __launch_bounds__(256) void k_gram_z64(GZArgs a) {
   constexpr int NI = KP / 16;
   constexpr int PC = 32;  // TRs per staged chunk
   constexpr int SM1 = PC * 64 + KP * (PC + 1), SM2 = 2 * KP * 65;
@@ -1528,7 +1617,7 @@ __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
   const int cg = threadIdx.x & 15, rg = threadIdx.x >> 4;
   const int qt = blockIdx.x, i = blockIdx.y;
   const int64_t q0 = 64 * (int64_t)qt;
-  const double* G = a.G + (int64_t)i * a.ldt * a.ldt;
+  const double* G = a.G64 + (int64_t)i * a.ldt * a.ldt;
   double acc[NI][4];
 #pragma unroll
   for (int u = 0; u < NI; ++u)
@@ -1728,7 +1817,10 @@ hipError_t launch_gram_build(hipStream_t st, int prec, int npairs, int N, const 
 
 hipError_t launch_gram_iter(hipStream_t st, int kp, int N, const GZArgs& z, const GSArgs& g) {
   SRM_KP_SWITCH(kp,
-      hipLaunchKernelGGL((k_gram_z<KP>), dim3(z.nq, N), dim3(256), 0, st, z);
+      if (z.G64)
+        hipLaunchKernelGGL((k_gram_z64<KP>), dim3(z.nq, N), dim3(256), 0, st, z);
+      else
+        hipLaunchKernelGGL((k_gram_z<KP>), dim3(z.nq, N), dim3(256), 0, st, z);
       hipLaunchKernelGGL((k_gram_gsum<KP>), dim3(N), dim3(256), 0, st, g));
   return hipGetLastError();
 }
