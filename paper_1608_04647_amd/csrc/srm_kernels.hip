@@ -733,16 +733,19 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
 
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
-  constexpr int TPC = 256 / CT;
-  constexpr int NJ = KP / TPC;
+  // Thread t holds the RJ x CW block: features RJ (t / 16) + u, TRs
+  // c0 + CW (t % 16) + m.
+  constexpr int RJ = KP / 16, CW = CT / 16;
   __shared__ double Zs[KP][CT];
-  __shared__ double Ps[KP][KP + 1];
+  __shared__ double Pt[KP][KP];  // P_i transposed: Pt[b][j] = P_i[j][b]
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * CT;
-  const int c = tid % CT, jr = tid / CT;
-  double out[NJ > 0 ? NJ : 1];
+  const int rg = tid / 16, cg = tid % 16;
+  double out[RJ][CW];
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) out[u] = 0.0;
+  for (int u = 0; u < RJ; ++u)
+#pragma unroll
+    for (int m = 0; m < CW; ++m) out[u][m] = 0.0;
   const int i0 = blockIdx.y * a.gsub;
   int i1 = i0 + a.gsub;
   if (i1 > a.N) i1 = a.N;
@@ -756,24 +759,37 @@ __global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
       Zs[j][cc] = s;
     }
     const double* P = a.P64 + (int64_t)i * KP * KP;
-    for (int idx = tid; idx < KP * KP; idx += 256) Ps[idx / KP][idx % KP] = P[idx];
+    for (int idx = tid; idx < KP * KP; idx += 256) Pt[idx % KP][idx / KP] = P[idx];
     __syncthreads();
     const double w = 1.0 / a.rho2[i];
+    double acc[RJ][CW];
 #pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const int j = jr + TPC * u;
-      double s = 0.0;
-#pragma unroll 8
-      for (int b = 0; b < KP; ++b) s += Ps[j][b] * Zs[b][c];
-      out[u] += w * s;
+    for (int u = 0; u < RJ; ++u)
+#pragma unroll
+      for (int m = 0; m < CW; ++m) acc[u][m] = 0.0;
+#pragma unroll 4
+    for (int b = 0; b < KP; ++b) {
+      double pv[RJ], zv[CW];
+#pragma unroll
+      for (int u = 0; u < RJ; ++u) pv[u] = Pt[b][RJ * rg + u];
+#pragma unroll
+      for (int m = 0; m < CW; ++m) zv[m] = Zs[b][CW * cg + m];
+#pragma unroll
+      for (int u = 0; u < RJ; ++u)
+#pragma unroll
+        for (int m = 0; m < CW; ++m) acc[u][m] += pv[u] * zv[m];
     }
+#pragma unroll
+    for (int u = 0; u < RJ; ++u)
+#pragma unroll
+      for (int m = 0; m < CW; ++m) out[u][m] += w * acc[u][m];
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) {
-    const int j = jr + TPC * u;
-    a.ygrp[((int64_t)blockIdx.y * KP + j) * a.ldt + c0 + c] = out[u];
-  }
+  for (int u = 0; u < RJ; ++u)
+#pragma unroll
+    for (int m = 0; m < CW; ++m)
+      a.ygrp[((int64_t)blockIdx.y * KP + RJ * rg + u) * a.ldt + c0 + CW * cg + m] = out[u][m];
 }
 
 // ---------------------------------------------------------------------------
