@@ -899,7 +899,9 @@ srm_status srm_map(srm_ctx* c, int32_t i, int32_t j, const float* X_new, int64_t
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
   // S_new = W_i^T (X_new - mu_i) in column chunks held in the Y-group
   // scratch (free between iterations), then Y = A_j (P_j S_new).
-  const size_t cap_cols = (size_t)p.ngrp * p.ldt * 8 / ((size_t)p.KP * 4) / 64 * 64;
+  // S_new chunks (k rows of float) in the Y-group buffer (ngrp KP ldt
+  // doubles): at least 2 ldt >= 128 columns per chunk.
+  const size_t cap_cols = (size_t)p.ngrp * p.KP * p.ldt * 8 / ((size_t)p.k * 4) / 64 * 64;
   if (cap_cols < 64) return fail(SRM_E_WORKSPACE, "map scratch too small");
   float* sbuf = c->at<float>(p.o_ygrp);
   srm_status sa = ensure_a(c, i);

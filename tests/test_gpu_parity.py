@@ -230,6 +230,21 @@ def test_map_matches_oracle(prec):
         assert err <= BAR[prec]
 
 
+def test_map_single_subject_full_k():
+    """srm_map with one subject and k = 128 (the scratch chunking at its
+    tightest) equals the oracle's projection W W^T (X_new - mu)."""
+    srm = _srm()
+    w = synth.Workload("map1", 1, 200, 200, 160, 128, 2)
+    d = synth.generate(w, seed=7)
+    g = srm.SRM(d["X"], w.k, prec="fp32", W0=d["W0"])
+    g.fit(w.n_iter)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    Xn = np.random.default_rng(3).standard_normal((200, 700)).astype(np.float32)
+    out = g.map(0, 0, Xn).cpu().numpy().astype(np.float64)
+    ref = ora["W"][0] @ (ora["W"][0].T @ (Xn.astype(np.float64) - ora["mu"][0][:, None]))
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= BAR["fp32"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
 def test_zscore_matches_oracle(prec):
     """Standardised input (Sec. IV-A, reading R14): voxels given very different
