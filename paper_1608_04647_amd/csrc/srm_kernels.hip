@@ -1030,6 +1030,43 @@ __global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
 // rho_i^2 = (c_i - 2 tr(W_i^T A_i) + t tau) / (t v_i).
 // ---------------------------------------------------------------------------
 
+// C = A B for KP x KP FP64 matrices in LDS (row stride ld), zero padded
+// beyond k: thread t holds the block rows t / 16 + 16 u, columns
+// t % 16 + 16 v (256 threads).
+template <int KP>
+__device__ __forceinline__ void mm_blk(const double* A, const double* B, int ld, int k,
+                                       double (&c)[KP / 16][KP / 16]) {
+  constexpr int RB = KP / 16;
+  const int rg = threadIdx.x / 16, cg = threadIdx.x % 16;
+#pragma unroll
+  for (int u = 0; u < RB; ++u)
+#pragma unroll
+    for (int v = 0; v < RB; ++v) c[u][v] = 0.0;
+  for (int kk = 0; kk < k; ++kk) {
+    double av[RB], bv[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) av[u] = A[(rg + 16 * u) * ld + kk];
+#pragma unroll
+    for (int v = 0; v < RB; ++v) bv[v] = B[kk * ld + cg + 16 * v];
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+      for (int v = 0; v < RB; ++v) c[u][v] += av[u] * bv[v];
+  }
+}
+
+__device__ double block_max256(double v, double* red /* >= 4 */) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return r;
+}
+
 template <int KP, int NT>
 __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
@@ -1040,8 +1077,10 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr bool IN_LDS = KP <= 96;
   constexpr int MAXP = (KP + 1) / 2;
   constexpr int NE = (KP * KP + NT - 1) / NT;  // product entries per thread
-  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
+  // A third buffer serves the Newton-Schulz iteration of the warm path.
+  __shared__ double lds[IN_LDS ? (WARM ? 3 : 2) * KP * LD : 1];
   __shared__ double cs_[MAXP], sn_[MAXP];
+  __shared__ double red[4];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
   __shared__ double isq[KP];  // lambda_j^-1/2
@@ -1065,6 +1104,97 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   }
   const bool warm = WARM && a.sc->polar_warm != 0;
   if constexpr (WARM) {
+    // Warm path: P_i = G_i^{-1/2} by the Newton-Schulz iteration
+    // X <- X + X E / 2, E = I - X G X, from the previous iteration's P_i
+    // (quadratic convergence while the Gram changes little between
+    // iterations).  It is taken when E vanishes to rounding and
+    // |X|_F^2 |G|_F < 1e13, which certifies lambda_min > 1e-13 lambda_max;
+    // otherwise the Jacobi eigensolver below decides.
+    if (warm && IN_LDS && NT == 256) {
+      constexpr int RB = KP / 16;
+      double* X = G + KP * LD;
+      double* B = X + KP * LD;
+      const double* Pp = a.P64 + (int64_t)i * KP * KP;
+      for (int idx = tid; idx < KP * KP; idx += NT) {
+        const int p = idx / KP, q = idx % KP;
+        X[p * LD + q] = Pp[idx];
+        if (p >= m || q >= m) G[p * LD + q] = 0.0;  // zero padding up to KP
+      }
+      __syncthreads();
+      const int rg = tid / 16, cg = tid % 16;
+      double c[RB][RB];
+      double emax = 1.0;
+      for (int it = 0; it < 8; ++it) {
+        mm_blk<KP>(G, X, LD, k, c);  // T = G X
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+        __syncthreads();
+        mm_blk<KP>(X, B, LD, k, c);  // X G X
+        double em = 0.0;
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+          for (int v = 0; v < RB; ++v) {
+            const int p = rg + 16 * u, q = cg + 16 * v;
+            c[u][v] = (p < k && q < k) ? (p == q ? 1.0 : 0.0) - c[u][v] : 0.0;
+            em = fmax(em, fabs(c[u][v]));
+          }
+        emax = block_max256(em, red);  // also orders the reads of B
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+        __syncthreads();
+        if (emax <= 1e-14 || !(emax < 0.5)) break;
+        mm_blk<KP>(X, B, LD, k, c);  // X E
+        __syncthreads();
+        // X <- X + (X E + E X) / 4: the symmetric part of X + X E / 2
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+        __syncthreads();
+        for (int idx = tid; idx < KP * KP; idx += NT) {
+          const int p = idx / KP, q = idx % KP;
+          if (p < q) {
+            const double d = 0.25 * (B[p * LD + q] + B[q * LD + p]);
+            X[p * LD + q] += d;
+            X[q * LD + p] += d;
+          } else if (p == q) {
+            X[p * LD + p] += 0.5 * B[p * LD + p];
+          }
+        }
+        __syncthreads();
+      }
+      // |X|_F^2, |G|_F^2 and tr(G X) = sum of the singular values of A_i
+      double nx = 0.0, ng = 0.0, tgx = 0.0;
+      for (int idx = tid; idx < k * k; idx += NT) {
+        const int p = idx / k, q = idx % k;
+        const double x = X[p * LD + q], gv = G[p * LD + q];
+        nx += x * x;
+        ng += gv * gv;
+        tgx += gv * X[q * LD + p];
+      }
+      nx = block_sum256(nx, red);
+      ng = block_sum256(ng, red);
+      tgx = block_sum256(tgx, red);
+      if (emax <= 1e-12 && nx * sqrt(ng) < 1e13) {
+        double* P = a.P64 + (int64_t)i * KP * KP;
+        for (int idx = tid; idx < KP * KP; idx += NT) {
+          const int p = idx / KP, q = idx % KP;
+          P[idx] = (p < k && q < k) ? 0.5 * (X[p * LD + q] + X[q * LD + p]) : 0.0;
+        }
+        if (tid == 0) {
+          const double t = (double)a.t;
+          a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
+        }
+        return;
+      }
+      __syncthreads();  // not taken: G is unchanged; the eigensolver decides
+    }
     const double* Vp = a.vprev + (int64_t)i * KP * KP;
     for (int idx = tid; idx < m * m; idx += NT) {
       const int p = idx / m, q = idx % m;
