@@ -283,6 +283,7 @@ class SRM:
         if getattr(self, "_ctx", None):
             _lib.srm_free(self._ctx)
             self._ctx = None
+            self._torch.cuda.synchronize()
         self._ws = None
 
     def __del__(self):
