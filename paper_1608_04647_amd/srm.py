@@ -22,6 +22,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python -m paper_1608_04647_amd.build`")
 
+# PyTorch ships its own HIP runtime.  Loading it first makes libsrm.so bind to
+# that same runtime (by soname); loaded the other way round, the process would
+# hold two HIP runtimes and the library's streams would not see torch's device
+# state.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 SRM_OK, SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_HIP, SRM_E_RANK, SRM_E_NOTPD, \

@@ -115,3 +115,11 @@ def test_binding_refuses_missing_device():
         pytest.skip("a device is present")
     with pytest.raises(srm.SRMError):
         srm.SRM([np.zeros((10, 8), np.float32)], 2)
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads PyTorch's HIP runtime before libsrm.so, so the
+    process maps exactly one libamdhip64 (two runtimes would not share
+    streams or device state)."""
+    maps = [l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l]
+    assert len(set(maps)) == 1, sorted(set(maps))
