@@ -216,7 +216,7 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_signew = take((size_t)p.KP * p.KP * 8);
   p.o_M = take((size_t)p.KP * p.KP * 8);
   p.o_prepwork = take((size_t)2 * p.KP * (p.KP + 1) * 8);
-  p.o_polwork = take(p.KP > 96 ? (size_t)p.N * 2 * p.KP * (p.KP + 1) * 8 : 8);
+  p.o_polwork = take(p.KP > 80 ? (size_t)p.N * 3 * p.KP * (p.KP + 1) * 8 : 8);
   p.o_vprev = take((size_t)p.N * p.KP * p.KP * 8);
   p.o_sc = take(sizeof(Scalars));
   p.o_ll = take(sizeof(double) * kLLCapacity);

@@ -179,7 +179,7 @@ struct QArgs {
   const double* c;
   double* rho2;
   double* P64;
-  double* work;   // [N][2][KP][KP+1] global scratch (KP > 96)
+  double* work;   // [N][3][KP][KP+1] global scratch (KP > 80)
   double* vprev;  // [N][KP][KP] eigenvectors of the previous iteration
   Scalars* sc;
   int32_t k;

@@ -1070,22 +1070,22 @@ __device__ double block_max256(double v, double* red /* >= 4 */) {
 template <int KP, int NT>
 __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
-  // G and V live in LDS for K padding <= 96 (two workgroups per CU up to
-  // 80), in global scratch above; warm start up to 80 (its product passes
-  // go through registers).
+  // Three KP x KP buffers (G; V or the Newton-Schulz iterate X; a product
+  // B) live in LDS for K padding <= 80, in global scratch above.  The
+  // Jacobi solver is warm-started from stored eigenvectors up to 80 (its
+  // product passes go through registers).
   constexpr bool WARM = KP <= 80;
-  constexpr bool IN_LDS = KP <= 96;
+  constexpr bool IN_LDS = KP <= 80;
   constexpr int MAXP = (KP + 1) / 2;
   constexpr int NE = (KP * KP + NT - 1) / NT;  // product entries per thread
-  // A third buffer serves the Newton-Schulz iteration of the warm path.
-  __shared__ double lds[IN_LDS ? (WARM ? 3 : 2) * KP * LD : 1];
+  __shared__ double lds[IN_LDS ? 3 * KP * LD : 1];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ double red[4];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
   __shared__ double isq[KP];  // lambda_j^-1/2
   const int i = blockIdx.x, tid = threadIdx.x, k = a.k;
-  double* G = IN_LDS ? lds : a.work + (int64_t)i * 2 * KP * LD;
+  double* G = IN_LDS ? lds : a.work + (int64_t)i * 3 * KP * LD;
   double* V = G + KP * LD;
   const Subject su = a.subj[i];
   const int m = (k + 1) & ~1;  // even player count; index k (if k odd) is a dummy
@@ -1103,14 +1103,14 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
     G[p * LD + q] = s;
   }
   const bool warm = WARM && a.sc->polar_warm != 0;
-  if constexpr (WARM) {
+  {
     // Warm path: P_i = G_i^{-1/2} by the Newton-Schulz iteration
     // X <- X + X E / 2, E = I - X G X, from the previous iteration's P_i
     // (quadratic convergence while the Gram changes little between
     // iterations).  It is taken when E vanishes to rounding and
     // |X|_F^2 |G|_F < 1e13, which certifies lambda_min > 1e-13 lambda_max;
     // otherwise the Jacobi eigensolver below decides.
-    if (warm && IN_LDS && NT == 256) {
+    if (a.sc->polar_warm != 0 && NT == 256) {
       constexpr int RB = KP / 16;
       double* X = G + KP * LD;
       double* B = X + KP * LD;
@@ -1195,6 +1195,8 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
       }
       __syncthreads();  // not taken: G is unchanged; the eigensolver decides
     }
+  }
+  if constexpr (WARM) {
     const double* Vp = a.vprev + (int64_t)i * KP * KP;
     for (int idx = tid; idx < m * m; idx += NT) {
       const int p = idx / m, q = idx % m;
