@@ -827,22 +827,26 @@ __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
   return ok;
 }
 
-// X = L^-1 for lower-triangular L (column-parallel forward substitution).
+// X = L^-1 for lower-triangular L: forward elimination of L X = I, one row
+// of L per step with all columns updated in parallel.
 __device__ void tri_inv_lower(const double* L, double* X, int k, int ld) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < k * k; idx += 256) {
     const int r = idx / k, c = idx % k;
-    if (r < c) X[r * ld + c] = 0.0;
-  }
-  for (int c = tid; c < k; c += 256) {
-    X[c * ld + c] = 1.0 / L[c * ld + c];
-    for (int r = c + 1; r < k; ++r) {
-      double s = 0.0;
-      for (int m = c; m < r; ++m) s += L[r * ld + m] * X[m * ld + c];
-      X[r * ld + c] = -s / L[r * ld + r];
-    }
+    X[r * ld + c] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
+  for (int m = 0; m < k; ++m) {
+    const double inv = 1.0 / L[m * ld + m];
+    for (int c = tid; c <= m; c += 256) X[m * ld + c] *= inv;
+    __syncthreads();
+    const int w = m + 1;  // nonzero columns of rows > m so far
+    for (int idx = tid; idx < (k - 1 - m) * w; idx += 256) {
+      const int r = m + 1 + idx / w, c = idx % w;
+      X[r * ld + c] -= L[r * ld + m] * X[m * ld + c];
+    }
+    __syncthreads();
+  }
 }
 
 // out = X^T X for lower-triangular X (full symmetric result, row-major ldo).
@@ -975,27 +979,34 @@ __global__ __launch_bounds__(256) void k_post_s(SArgs a) {
 // Sigma_s = M + S S^T / t (Eq. 11), tau = tr(Sigma_s), log-likelihood.
 // ---------------------------------------------------------------------------
 
+// Sigma_s_new = M + S S^T / t (Eq. 11), symmetrised: one entry per thread,
+// the column-tile partials of S S^T summed in a fixed order.
+template <int KP>
+__global__ __launch_bounds__(256) void k_post_sig(FinArgs a) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= KP * KP) return;
+  const int p = idx / KP, q = idx % KP;
+  double v = 0.0;
+  if (p < a.k && q < a.k) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < a.nblk; ++b) {
+      s1 += a.sspart[(int64_t)b * KP * KP + p * KP + q];
+      s2 += a.sspart[(int64_t)b * KP * KP + q * KP + p];
+    }
+    const double v1 = a.M[p * KP + q] + s1 / (double)a.t;
+    const double v2 = a.M[q * KP + p] + s2 / (double)a.t;
+    v = 0.5 * (v1 + v2);
+  }
+  a.sig_new[idx] = v;
+}
+
+// tr(Sigma_s_new) and the log-likelihood of the parameters entering the step.
 template <int KP>
 __global__ __launch_bounds__(256) void k_post_fin(FinArgs a) {
   __shared__ double red[4];
   const int tid = threadIdx.x;
   double tau = 0.0;
-  for (int idx = tid; idx < KP * KP; idx += 256) {
-    const int p = idx / KP, q = idx % KP;
-    double v = 0.0;
-    if (p < a.k && q < a.k) {
-      double s1 = 0.0, s2 = 0.0;
-      for (int b = 0; b < a.nblk; ++b) {
-        s1 += a.sspart[(int64_t)b * KP * KP + p * KP + q];
-        s2 += a.sspart[(int64_t)b * KP * KP + q * KP + p];
-      }
-      const double v1 = a.M[p * KP + q] + s1 / (double)a.t;
-      const double v2 = a.M[q * KP + p] + s2 / (double)a.t;
-      v = 0.5 * (v1 + v2);
-    }
-    a.sig_new[idx] = v;
-    if (p == q) tau += v;
-  }
+  for (int p = tid; p < a.k; p += 256) tau += a.sig_new[p * KP + p];
   tau = block_sum256(tau, red);
   if (tid == 0) {
     double tr = 0.0;
@@ -1905,7 +1916,9 @@ hipError_t launch_post_s(hipStream_t st, int kp, int prec, int nblk,
   return hipGetLastError();
 }
 hipError_t launch_post_fin(hipStream_t st, int kp, const FinArgs& a) {
-  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_post_fin<KP>), dim3(1), dim3(256), 0, st, a));
+  SRM_KP_SWITCH(kp,
+      hipLaunchKernelGGL((k_post_sig<KP>), dim3((KP * KP + 255) / 256), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_post_fin<KP>), dim3(1), dim3(256), 0, st, a));
   return hipGetLastError();
 }
 hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
