@@ -229,72 +229,92 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) acc[mb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Operands of step tb + 1 are loaded while step tb's products run
+    // (double buffer).
     if constexpr (PREC == P_FP32) {
       const float* X = (const float*)a.xh + rowt * a.ldt;  // uniform
       const int ld = (int)a.ldt;
       const int nstep = ld / 16;
-      for (int tb = 0; tb < nstep; ++tb) {
-        float4 x4[4];
+      float4 x4[2][4], s4[2][NB];
+      auto load = [&](int tb, int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           if (mb < 2 || h1)
-            x4[mb] = *(const float4*)(X + (16 * mb + n) * ld + 16 * tb + 4 * g);
+            x4[b][mb] = *(const float4*)(X + (16 * mb + n) * ld + 16 * tb + 4 * g);
           else
-            x4[mb] = make_float4(0.f, 0.f, 0.f, 0.f);
+            x4[b][mb] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         const float4* SR = (const float4*)a.sh + tb * NB * 64;
-        float4 s4[NB];
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) s4[jb] = SR[jb * 64 + lane];
+        for (int jb = 0; jb < NB; ++jb) s4[b][jb] = SR[jb * 64 + lane];
+      };
+      auto comp = [&](int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           if (mb >= 2 && !h1) continue;
 #pragma unroll
           for (int jb = 0; jb < NB; ++jb) {
-            acc[mb][jb] = mfma_f32(x4[mb].x, s4[jb].x, acc[mb][jb]);
-            acc[mb][jb] = mfma_f32(x4[mb].y, s4[jb].y, acc[mb][jb]);
-            acc[mb][jb] = mfma_f32(x4[mb].z, s4[jb].z, acc[mb][jb]);
-            acc[mb][jb] = mfma_f32(x4[mb].w, s4[jb].w, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[b][mb].x, s4[b][jb].x, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[b][mb].y, s4[b][jb].y, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[b][mb].z, s4[b][jb].z, acc[mb][jb]);
+            acc[mb][jb] = mfma_f32(x4[b][mb].w, s4[b][jb].w, acc[mb][jb]);
           }
         }
+      };
+      load(0, 0);
+      for (int tb = 0; tb < nstep; tb += 2) {
+        if (tb + 1 < nstep) load(tb + 1, 1);
+        comp(0);
+        if (tb + 1 >= nstep) break;
+        if (tb + 2 < nstep) load(tb + 2, 0);
+        comp(1);
       }
     } else {
       const uint16_t* XH = (const uint16_t*)a.xh + rowt * a.ldt;  // uniform
       const uint16_t* XL = (const uint16_t*)a.xl + rowt * a.ldt;
       const int ld = (int)a.ldt;
       const int nstep = ld / 32;
-      for (int tb = 0; tb < nstep; ++tb) {
-        const uint4* SH = (const uint4*)a.sh + tb * NB * 64;
-        const uint4* SL = (const uint4*)a.sl + tb * NB * 64;
-        uint4 xh4[4], xl4[4];
+      uint4 xh4[2][4], xl4[2][4], sh4[2][NB], sl4[2][NB];
+      auto load = [&](int tb, int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           const int o = (16 * mb + n) * ld + 32 * tb + 8 * g;
           if (mb < 2 || h1) {
-            xh4[mb] = *(const uint4*)(XH + o);
-            if constexpr (PREC == P_BF16X2) xl4[mb] = *(const uint4*)(XL + o);
+            xh4[b][mb] = *(const uint4*)(XH + o);
+            if constexpr (PREC == P_BF16X2) xl4[b][mb] = *(const uint4*)(XL + o);
           } else {
-            xh4[mb] = make_uint4(0, 0, 0, 0);
-            xl4[mb] = make_uint4(0, 0, 0, 0);
+            xh4[b][mb] = make_uint4(0, 0, 0, 0);
+            xl4[b][mb] = make_uint4(0, 0, 0, 0);
           }
         }
-        uint4 sh4[NB], sl4[NB];
+        const uint4* SH = (const uint4*)a.sh + tb * NB * 64;
+        const uint4* SL = (const uint4*)a.sl + tb * NB * 64;
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          sh4[jb] = SH[jb * 64 + lane];
-          sl4[jb] = SL[jb * 64 + lane];
+          sh4[b][jb] = SH[jb * 64 + lane];
+          sl4[b][jb] = SL[jb * 64 + lane];
         }
+      };
+      auto comp = [&](int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           if (mb >= 2 && !h1) continue;
 #pragma unroll
           for (int jb = 0; jb < NB; ++jb) {
-            acc[mb][jb] = mfma_bf16(xh4[mb], sh4[jb], acc[mb][jb]);
-            acc[mb][jb] = mfma_bf16(xh4[mb], sl4[jb], acc[mb][jb]);
+            acc[mb][jb] = mfma_bf16(xh4[b][mb], sh4[b][jb], acc[mb][jb]);
+            acc[mb][jb] = mfma_bf16(xh4[b][mb], sl4[b][jb], acc[mb][jb]);
             if constexpr (PREC == P_BF16X2)
-              acc[mb][jb] = mfma_bf16(xl4[mb], sh4[jb], acc[mb][jb]);
+              acc[mb][jb] = mfma_bf16(xl4[b][mb], sh4[b][jb], acc[mb][jb]);
           }
         }
+      };
+      load(0, 0);
+      for (int tb = 0; tb < nstep; tb += 2) {
+        if (tb + 1 < nstep) load(tb + 1, 1);
+        comp(0);
+        if (tb + 1 >= nstep) break;
+        if (tb + 2 < nstep) load(tb + 2, 0);
+        comp(1);
       }
     }
     // Accumulator lane l holds A[rowt + 16 mb + 4 g + i][16 jb + n]; two
