@@ -378,38 +378,38 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
 #pragma unroll
     for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int nblk = sl.nrows / 32;
+    // Operands of the next step are loaded while the current step's
+    // products run (double buffer).  FP32 steps are 16-row halves of the
+    // 32-row A records; BF16 steps are whole records (the K = 32 products
+    // consume all 32 rows at once).
     const int ld = (int)a.ldt;
-    for (int blk = 0; blk < nblk; ++blk) {
-      const int64_t row0 = sl.row0 + 32 * blk;
-      const int64_t rb = row0 / 32;
-      const int64_t xbase = row0 * a.ldt + cbase;  // wave-uniform
-      if constexpr (PREC == P_FP32) {
-        const float4* AR = (const float4*)a.ah + rb * NB * 128;  // uniform
-        float av[NB][8];
+    if constexpr (PREC == P_FP32) {
+      const int nstep = sl.nrows / 16;
+      float4 av[2][NB], xv[2][4];
+      auto load = [&](int hs, int b) __attribute__((always_inline)) {
+        const int64_t row0 = sl.row0 + 32 * (hs >> 1);
+        const int h = hs & 1;
+        const float4* AR = (const float4*)a.ah + (row0 / 32) * NB * 128;  // uniform
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-          const int rec = jb * 64 + lane;
-          const float4 p0 = AR[rec * 2], p1 = AR[rec * 2 + 1];
-          av[jb][0] = p0.x; av[jb][1] = p0.y; av[jb][2] = p0.z; av[jb][3] = p0.w;
-          av[jb][4] = p1.x; av[jb][5] = p1.y; av[jb][6] = p1.z; av[jb][7] = p1.w;
-        }
+        for (int jb = 0; jb < NB; ++jb) av[b][jb] = AR[(jb * 64 + lane) * 2 + h];
         if (do_z) {
-          const float* X = (const float*)a.xh + xbase;
-          float4 xv[8];
+          const float* X = (const float*)a.xh + row0 * a.ldt + cbase;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int o = (4 * g + (e & 3) + 16 * (e >> 2)) * ld + 4 * n;
-            xv[e] = *(const float4*)(X + o);
-          }
+          for (int i = 0; i < 4; ++i)
+            xv[b][i] = *(const float4*)(X + (16 * h + 4 * g + i) * ld + 4 * n);
+        }
+      };
+      auto comp = [&](int b) __attribute__((always_inline)) {
+        if (do_z) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int jb = 0; jb < NB; ++jb) {
-              acc[jb][0] = mfma_f32(av[jb][e], xv[e].x, acc[jb][0]);
-              acc[jb][1] = mfma_f32(av[jb][e], xv[e].y, acc[jb][1]);
-              acc[jb][2] = mfma_f32(av[jb][e], xv[e].z, acc[jb][2]);
-              acc[jb][3] = mfma_f32(av[jb][e], xv[e].w, acc[jb][3]);
+              const float ae = ((const float*)&av[b][jb])[i];
+              acc[jb][0] = mfma_f32(ae, xv[b][i].x, acc[jb][0]);
+              acc[jb][1] = mfma_f32(ae, xv[b][i].y, acc[jb][1]);
+              acc[jb][2] = mfma_f32(ae, xv[b][i].z, acc[jb][2]);
+              acc[jb][3] = mfma_f32(ae, xv[b][i].w, acc[jb][3]);
             }
         }
         if (do_g) {
@@ -420,44 +420,68 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
             for (int j2 = j1; j2 < NB; ++j2, ++p)
               if ((p & 3) == wave)
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                  gacc[p >> 2] = mfma_f32(av[j1][e], av[j2][e], gacc[p >> 2]);
+                for (int i = 0; i < 4; ++i)
+                  gacc[p >> 2] = mfma_f32(((const float*)&av[b][j1])[i],
+                                          ((const float*)&av[b][j2])[i], gacc[p >> 2]);
         }
-      } else {
+      };
+      if (nstep > 0) load(0, 0);
+      for (int hs = 0; hs < nstep; hs += 2) {
+        if (hs + 1 < nstep) load(hs + 1, 1);
+        comp(0);
+        if (hs + 1 >= nstep) break;
+        if (hs + 2 < nstep) load(hs + 2, 0);
+        comp(1);
+      }
+    } else {
+      const int nblk = sl.nrows / 32;
+      // Above KP = 80 with both halves of X, a second A buffer would spill:
+      // there A is loaded at the start of its step (L2-resident, shared by
+      // the workgroup's four waves) and only X is double-buffered.
+      constexpr int DA = (PREC == P_BF16X2 && KP > 80) ? 1 : 2;
+      uint4 ah[DA][NB], al[DA][NB];
+      uint2 xv[2][8], xw[2][8];
+      auto load_a = [&](int blk, int b) __attribute__((always_inline)) {
+        const int64_t rb = (sl.row0 + 32 * blk) / 32;
         const uint4* AH = (const uint4*)a.ah + rb * NB * 64;  // uniform
         const uint4* AL = (const uint4*)a.al + rb * NB * 64;
-        uint4 ah[NB], al[NB];
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          ah[jb] = AH[jb * 64 + lane];
-          al[jb] = AL[jb * 64 + lane];
+          ah[b][jb] = AH[jb * 64 + lane];
+          al[b][jb] = AL[jb * 64 + lane];
         }
+      };
+      auto load = [&](int blk, int b) __attribute__((always_inline)) {
+        const int64_t row0 = sl.row0 + 32 * blk;
+        if constexpr (DA == 2) load_a(blk, b);
         if (do_z) {
+          const int64_t xbase = row0 * a.ldt + cbase;  // wave-uniform
           const uint16_t* XH = (const uint16_t*)a.xh + xbase;
           const uint16_t* XL = (const uint16_t*)a.xl + xbase;
-          uint2 xv[8], xw[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int o = (4 * g + (e & 3) + 16 * (e >> 2)) * ld + 4 * n;
-            xv[e] = *(const uint2*)(XH + o);
-            if constexpr (PREC == P_BF16X2) xw[e] = *(const uint2*)(XL + o);
+            xv[b][e] = *(const uint2*)(XH + o);
+            if constexpr (PREC == P_BF16X2) xw[b][e] = *(const uint2*)(XL + o);
           }
+        }
+      };
+      auto comp = [&](int blk, int b) __attribute__((always_inline)) {
+        const int ba = DA == 2 ? b : 0;
+        if constexpr (DA == 1) load_a(blk, 0);
+        if (do_z) {
           // In-register 8x4 transpose: operand q holds column 4n+q of the
           // 8 rows, two rows per dword.
           uint4 bh[4], bl[4];
 #pragma unroll
           for (int d = 0; d < 4; ++d) {
-            const uint2 u0 = xv[2 * d], u1 = xv[2 * d + 1];
-            const uint32_t c0 = (u0.x & 0xffffu) | (u1.x << 16);
-            const uint32_t c1 = (u0.x >> 16) | (u1.x & 0xffff0000u);
-            const uint32_t c2 = (u0.y & 0xffffu) | (u1.y << 16);
-            const uint32_t c3 = (u0.y >> 16) | (u1.y & 0xffff0000u);
-            ((uint32_t*)&bh[0])[d] = c0;
-            ((uint32_t*)&bh[1])[d] = c1;
-            ((uint32_t*)&bh[2])[d] = c2;
-            ((uint32_t*)&bh[3])[d] = c3;
+            const uint2 u0 = xv[b][2 * d], u1 = xv[b][2 * d + 1];
+            ((uint32_t*)&bh[0])[d] = (u0.x & 0xffffu) | (u1.x << 16);
+            ((uint32_t*)&bh[1])[d] = (u0.x >> 16) | (u1.x & 0xffff0000u);
+            ((uint32_t*)&bh[2])[d] = (u0.y & 0xffffu) | (u1.y << 16);
+            ((uint32_t*)&bh[3])[d] = (u0.y >> 16) | (u1.y & 0xffff0000u);
             if constexpr (PREC == P_BF16X2) {
-              const uint2 w0 = xw[2 * d], w1 = xw[2 * d + 1];
+              const uint2 w0 = xw[b][2 * d], w1 = xw[b][2 * d + 1];
               ((uint32_t*)&bl[0])[d] = (w0.x & 0xffffu) | (w1.x << 16);
               ((uint32_t*)&bl[1])[d] = (w0.x >> 16) | (w1.x & 0xffff0000u);
               ((uint32_t*)&bl[2])[d] = (w0.y & 0xffffu) | (w1.y << 16);
@@ -468,10 +492,10 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int jb = 0; jb < NB; ++jb) {
-              acc[jb][q] = mfma_bf16(ah[jb], bh[q], acc[jb][q]);
-              acc[jb][q] = mfma_bf16(al[jb], bh[q], acc[jb][q]);
+              acc[jb][q] = mfma_bf16(ah[ba][jb], bh[q], acc[jb][q]);
+              acc[jb][q] = mfma_bf16(al[ba][jb], bh[q], acc[jb][q]);
               if constexpr (PREC == P_BF16X2)
-                acc[jb][q] = mfma_bf16(ah[jb], bl[q], acc[jb][q]);
+                acc[jb][q] = mfma_bf16(ah[ba][jb], bl[q], acc[jb][q]);
             }
         }
         if (do_g) {
@@ -481,13 +505,21 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
 #pragma unroll
             for (int j2 = j1; j2 < NB; ++j2, ++p)
               if ((p & 3) == wave) {
-                gacc[p >> 2] = mfma_bf16(ah[j1], ah[j2], gacc[p >> 2]);
-                gacc[p >> 2] = mfma_bf16(ah[j1], al[j2], gacc[p >> 2]);
-                gacc[p >> 2] = mfma_bf16(al[j1], ah[j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(ah[ba][j1], ah[ba][j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(ah[ba][j1], al[ba][j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(al[ba][j1], ah[ba][j2], gacc[p >> 2]);
                 // lo*lo too: its error would scale with cond(A^T A) in W^T W.
-                gacc[p >> 2] = mfma_bf16(al[j1], al[j2], gacc[p >> 2]);
+                gacc[p >> 2] = mfma_bf16(al[ba][j1], al[ba][j2], gacc[p >> 2]);
               }
         }
+      };
+      if (nblk > 0) load(0, 0);
+      for (int blk = 0; blk < nblk; blk += 2) {
+        if (blk + 1 < nblk) load(blk + 1, 1);
+        comp(blk, 0);
+        if (blk + 1 >= nblk) break;
+        if (blk + 2 < nblk) load(blk + 2, 0);
+        comp(blk + 1, 1);
       }
     }
     // Z tile: lane holds Z[16 jb + 4 g + i][cbase + 4 n + q].
