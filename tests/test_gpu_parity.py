@@ -69,6 +69,8 @@ CASES = {
     "n1k1": synth.Workload("n1k1", 1, 40, 40, 16, 1, 5),
     # 500 TRs and k = 50: the batched workload's shape per subject
     "wide": synth.Workload("wide", 3, 200, 700, 500, 50, 4, sigma_lo=0.5, sigma_hi=2.0),
+    # the same shape with several 64-row chunks and slices per row range
+    "wide2": synth.Workload("wide2", 3, 20000, 30000, 500, 50, 3, sigma_lo=0.5, sigma_hi=2.0),
     # degenerate shapes: square maps (v_i = k), and the smallest problem
     # (t = 2, one voxel, k = 1)
     "vk": synth.Workload("vk", 3, 6, 6, 40, 6, 5),
