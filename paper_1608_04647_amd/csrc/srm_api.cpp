@@ -90,7 +90,7 @@ struct Plan {
          o_zpart = 0, o_gpart = 0, o_p64 = 0, o_rho2 = 0, o_ygrp = 0,
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
-         o_prepwork = 0, o_polwork = 0, o_vprev = 0, o_sc = 0, o_ll = 0, o_subj = 0,
+         o_polwork = 0, o_vprev = 0, o_sc = 0, o_ll = 0, o_subj = 0,
          o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0,
          o_G = 0, o_gz = 0, o_subjg = 0;
   size_t stage_bytes = 0;
@@ -215,7 +215,6 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_sigcur = take((size_t)p.KP * p.KP * 8);
   p.o_signew = take((size_t)p.KP * p.KP * 8);
   p.o_M = take((size_t)p.KP * p.KP * 8);
-  p.o_prepwork = take((size_t)2 * p.KP * (p.KP + 1) * 8);
   p.o_polwork = take(p.KP > 80 ? (size_t)p.N * 3 * p.KP * (p.KP + 1) * 8 : 8);
   p.o_vprev = take((size_t)p.N * p.KP * p.KP * 8);
   p.o_sc = take(sizeof(Scalars));
@@ -447,7 +446,7 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
     if ((e = launch_ereduce(st, p.KP, p.ncol_r, p.ngrp, ra)) != hipSuccess) return e;
   }
   PrepArgs pa{c->at<double>(p.o_rho2), c->at<double>(p.o_c), c->at<Subject>(p.o_subj),
-              c->at<double>(p.o_sigcur), c->at<double>(p.o_M), c->at<double>(p.o_prepwork),
+              c->at<double>(p.o_sigcur), c->at<double>(p.o_M),
               c->at<Scalars>(p.o_sc), p.N, p.k};
   {
     Phase ph(c, SRM_PHASE_POSTERIOR);

@@ -128,7 +128,6 @@ struct PrepArgs {
   const Subject* subj;
   const double* sig;  // [KP][KP] current Sigma_s
   double* M;          // [KP][KP] out (zero padded)
-  double* work;       // global scratch [2][KP][KP+1] (used when KP > 96)
   Scalars* sc;
   int32_t N;
   int32_t k;

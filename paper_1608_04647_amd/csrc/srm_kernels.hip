@@ -845,8 +845,8 @@ __global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense FP64 helpers for k x k matrices (one workgroup of 256 threads).
-// Storage row-major with leading dimension ld; pointers may be LDS or global.
+// Dense FP64 helpers for k x k matrices (one workgroup of 256 threads),
+// in place on one LDS matrix, row-major with leading dimension ld.
 // ---------------------------------------------------------------------------
 // In-place lower Cholesky (right-looking).  Returns false if not PD.
 __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
@@ -879,26 +879,66 @@ __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
   return ok;
 }
 
-// X = L^-1 for lower-triangular L: forward elimination of L X = I, one row
-// of L per step with all columns updated in parallel.
-__device__ void tri_inv_lower(const double* L, double* X, int k, int ld) {
+// In place: the lower triangle of A (a Cholesky factor L) becomes X = L^-1.
+// Forward elimination of L X = I, one pivot row per step with all rows below
+// it updated in parallel.  While step m runs, row r of the storage holds X's
+// columns c < m and L's columns c >= m.  Pivot row m is used unscaled
+// (1 / L_mm folded into the update) and scaled one step later, when nothing
+// reads it any more.  col: [k] doubles of scratch.
+__device__ void tri_inv_lower_inplace(double* A, int k, int ld, double* col) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < k * k; idx += 256) {
-    const int r = idx / k, c = idx % k;
-    X[r * ld + c] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
+  double prev_inv = 0.0;
   for (int m = 0; m < k; ++m) {
-    const double inv = 1.0 / L[m * ld + m];
-    for (int c = tid; c <= m; c += 256) X[m * ld + c] *= inv;
-    __syncthreads();
-    const int w = m + 1;  // nonzero columns of rows > m so far
-    for (int idx = tid; idx < (k - 1 - m) * w; idx += 256) {
-      const int r = m + 1 + idx / w, c = idx % w;
-      X[r * ld + c] -= L[r * ld + m] * X[m * ld + c];
+    const double inv = 1.0 / A[m * ld + m];
+    for (int r = m + 1 + tid; r < k; r += 256) col[r] = A[r * ld + m];
+    if (m > 0) {  // finish the previous pivot row
+      for (int c = tid; c < m - 1; c += 256) A[(m - 1) * ld + c] *= prev_inv;
+      if (tid == 0) A[(m - 1) * ld + m - 1] = prev_inv;
     }
     __syncthreads();
+    const int w = m + 1;
+    for (int idx = tid; idx < (k - 1 - m) * w; idx += 256) {
+      const int r = m + 1 + idx / w, c = idx % w;
+      const double l = col[r] * inv;
+      if (c < m)
+        A[r * ld + c] -= l * A[m * ld + c];
+      else
+        A[r * ld + m] = -l;
+    }
+    __syncthreads();
+    prev_inv = inv;
   }
+  if (k > 0) {
+    for (int c = tid; c < k - 1; c += 256) A[(k - 1) * ld + c] *= prev_inv;
+    if (tid == 0) A[(k - 1) * ld + k - 1] = prev_inv;
+  }
+  __syncthreads();
+}
+
+// In place: lower-triangular X (lower triangle of A) becomes the full
+// symmetric X^T X.  Entries above the diagonal are formed first (that
+// storage is free), the diagonal in diag[k], then mirrored down.
+__device__ void ltl_inplace(double* A, int k, int ld, double* diag) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int a = idx / k, b = idx % k;
+    if (a > b) continue;
+    double s = 0.0;
+    for (int m = b; m < k; ++m) s += A[m * ld + a] * A[m * ld + b];
+    if (a == b)
+      diag[a] = s;
+    else
+      A[a * ld + b] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int a = idx / k, b = idx % k;
+    if (a > b)
+      A[a * ld + b] = A[b * ld + a];
+    else if (a == b)
+      A[a * ld + a] = diag[a];
+  }
+  __syncthreads();
 }
 
 // out = X^T X for lower-triangular X (full symmetric result, row-major ldo).
@@ -916,18 +956,17 @@ __device__ void ltl(const double* X, int k, int ld, double* out, int ldo) {
 // ---------------------------------------------------------------------------
 // Posterior preparation (one workgroup): rho0 (Eq. 8), Cholesky of Sigma_s,
 // Sigma_s^-1, M = (Sigma_s^-1 + rho0 I)^-1 (Eq. 7), log|I + rho0 Sigma_s| and
-// the likelihood's data terms.
+// the likelihood's data terms.  One k x k matrix in LDS (up to 132 KB at
+// K padding 128); every factor and inverse is formed in place.
 // ---------------------------------------------------------------------------
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_post_prep(PrepArgs a) {
   constexpr int LD = KP + 1;
-  constexpr bool IN_LDS = KP <= 96;
-  __shared__ double lds[IN_LDS ? 2 * KP * LD : 1];
+  __shared__ double A[KP * LD];
+  __shared__ double vec[KP];
   __shared__ double red[4];
   __shared__ int flag;
-  double* A = IN_LDS ? lds : a.work;
-  double* B = IN_LDS ? lds + KP * LD : a.work + KP * LD;
   const int tid = threadIdx.x, k = a.k;
 
   double r0 = 0.0, vl = 0.0, cr = 0.0;
@@ -948,18 +987,18 @@ __global__ __launch_bounds__(256) void k_post_prep(PrepArgs a) {
   double ld1 = 0.0;
   for (int j = tid; j < k; j += 256) ld1 += 2.0 * log(A[j * LD + j]);
   ld1 = block_sum256(ld1, red);
-  tri_inv_lower(A, B, k, LD);
-  ltl(B, k, LD, A, LD);  // A = Sigma_s^-1
+  tri_inv_lower_inplace(A, k, LD, vec);
+  ltl_inplace(A, k, LD, vec);  // A = Sigma_s^-1
   for (int j = tid; j < k; j += 256) A[j * LD + j] += rho0;
   __syncthreads();
   ok = chol_lower(A, k, LD, &flag) && ok;
   double ld2 = 0.0;
   for (int j = tid; j < k; j += 256) ld2 += 2.0 * log(A[j * LD + j]);
   ld2 = block_sum256(ld2, red);
-  tri_inv_lower(A, B, k, LD);
+  tri_inv_lower_inplace(A, k, LD, vec);
   for (int idx = tid; idx < KP * KP; idx += 256) a.M[idx] = 0.0;
   __syncthreads();
-  ltl(B, k, LD, a.M, KP);
+  ltl(A, k, LD, a.M, KP);
   if (tid == 0) {
     a.sc->rho0 = rho0;
     a.sc->sum_vlogrho = svl;
