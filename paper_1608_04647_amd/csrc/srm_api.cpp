@@ -90,7 +90,7 @@ struct Plan {
          o_zpart = 0, o_gpart = 0, o_p64 = 0, o_rho2 = 0, o_ygrp = 0,
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
-         o_polwork = 0, o_vprev = 0, o_sc = 0, o_ll = 0, o_subj = 0,
+         o_polwork = 0, o_vprev = 0, o_pjac = 0, o_sc = 0, o_ll = 0, o_subj = 0,
          o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0,
          o_G = 0, o_gz = 0, o_subjg = 0;
   size_t stage_bytes = 0;
@@ -217,6 +217,7 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_M = take((size_t)p.KP * p.KP * 8);
   p.o_polwork = take(p.KP > 80 ? (size_t)p.N * 3 * p.KP * (p.KP + 1) * 8 : 8);
   p.o_vprev = take((size_t)p.N * p.KP * p.KP * 8);
+  p.o_pjac = take(sizeof(int32_t) * p.N);
   p.o_sc = take(sizeof(Scalars));
   p.o_ll = take(sizeof(double) * kLLCapacity);
   p.o_subj = take(sizeof(Subject) * p.N);
@@ -435,7 +436,8 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
   if (with_polar) {
     QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(o_tab), c->at<double>(p.o_c),
              c->at<double>(p.o_rho2), c->at<double>(p.o_p64), c->at<double>(p.o_polwork),
-             c->at<double>(p.o_vprev), c->at<Scalars>(p.o_sc), p.k, p.t};
+             c->at<double>(p.o_vprev), c->at<int32_t>(p.o_pjac), c->at<Scalars>(p.o_sc),
+             p.k, p.t};
     Phase ph(c, SRM_PHASE_POLAR);
     if ((e = launch_polar(st, p.KP, p.N, qa)) != hipSuccess) return e;
   }

@@ -180,6 +180,7 @@ struct QArgs {
   double* P64;
   double* work;   // [N][3][KP][KP+1] global scratch (KP > 80)
   double* vprev;  // [N][KP][KP] eigenvectors of the previous iteration
+  int32_t* jac;   // [N] 1: Newton-Schulz step not taken (KP > 80, set per launch)
   Scalars* sc;
   int32_t k;
   int64_t t;

@@ -1169,26 +1169,39 @@ __device__ double block_max256(double v, double* red /* >= 4 */) {
   return r;
 }
 
-template <int KP, int NT>
+// MODE: POLAR_BOTH runs the Newton-Schulz attempt and, if it is not taken,
+// the Jacobi solver in one launch (K padding <= 80).  Above 80 the two are
+// separate launches: POLAR_NS (256 threads) marks the subjects whose
+// attempt was not taken in a.jac, and POLAR_JAC (1024 threads, G in LDS,
+// V in global scratch) solves those.
+enum { POLAR_BOTH = 0, POLAR_NS = 1, POLAR_JAC = 2 };
+
+template <int KP, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr int LD = KP + 1;
   // Three KP x KP buffers (G; V or the Newton-Schulz iterate X; a product
-  // B) live in LDS for K padding <= 80, in global scratch above.  The
-  // Jacobi solver is warm-started from stored eigenvectors up to 80 (its
-  // product passes go through registers).
+  // B) live in LDS for K padding <= 80, in global scratch above (except G
+  // of the separate Jacobi launch, which is in LDS).  The Jacobi solver is
+  // warm-started from stored eigenvectors up to 80 (its product passes go
+  // through registers).
   constexpr bool WARM = KP <= 80;
   constexpr bool IN_LDS = KP <= 80;
+  constexpr bool G_LDS = IN_LDS || MODE == POLAR_JAC;
   constexpr int MAXP = (KP + 1) / 2;
   constexpr int NE = (KP * KP + NT - 1) / NT;  // product entries per thread
-  __shared__ double lds[IN_LDS ? 3 * KP * LD : 1];
+  __shared__ double lds[IN_LDS ? 3 * KP * LD : (G_LDS ? KP * LD : 1)];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ double red[4];
   __shared__ int pp_[MAXP], qq_[MAXP];
   __shared__ int rotated;
   __shared__ double isq[KP];  // lambda_j^-1/2
   const int i = blockIdx.x, tid = threadIdx.x, k = a.k;
-  double* G = IN_LDS ? lds : a.work + (int64_t)i * 3 * KP * LD;
-  double* V = G + KP * LD;
+  if constexpr (MODE == POLAR_JAC) {
+    if (a.jac[i] == 0) return;  // whole workgroup: the Newton-Schulz step was taken
+  }
+  double* const gw = a.work + (int64_t)i * 3 * KP * LD;
+  double* G = G_LDS ? lds : gw;
+  double* V = IN_LDS ? G + KP * LD : gw + KP * LD;
   const Subject su = a.subj[i];
   const int m = (k + 1) & ~1;  // even player count; index k (if k odd) is a dummy
   const int npair = m / 2;
@@ -1292,11 +1305,16 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
         if (tid == 0) {
           const double t = (double)a.t;
           a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
+          if (MODE == POLAR_NS) a.jac[i] = 0;
         }
         return;
       }
       __syncthreads();  // not taken: G is unchanged; the eigensolver decides
     }
+  }
+  if constexpr (MODE == POLAR_NS) {
+    if (tid == 0) a.jac[i] = 1;
+    return;
   }
   if constexpr (WARM) {
     const double* Vp = a.vprev + (int64_t)i * KP * KP;
@@ -1409,13 +1427,30 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
         G[q * LD + r] = cy * m10 - sy * m11;
         G[q * LD + t] = sy * m10 + cy * m11;
       }
-      for (int idx = tid; idx < npair * m; idx += NT) {
-        const int x = idx / m, j = idx % m;
-        const int p = pp_[x], q = qq_[x];
-        const double c = cs_[x], s = sn_[x];
-        const double vp = V[j * LD + p], vq = V[j * LD + q];
-        V[j * LD + p] = c * vp - s * vq;
-        V[j * LD + q] = s * vp + c * vq;
+      // V <- V J: all of a thread's loads first, then its stores (V may be
+      // in global memory, where a load after each store would wait).
+      {
+        constexpr int NV = (MAXP * KP + NT - 1) / NT;
+        double vp[NV], vq[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          const int idx = tid + NT * u;
+          if (idx < npair * m) {
+            const int x = idx / m, j = idx % m;
+            vp[u] = V[j * LD + pp_[x]];
+            vq[u] = V[j * LD + qq_[x]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          const int idx = tid + NT * u;
+          if (idx < npair * m) {
+            const int x = idx / m, j = idx % m;
+            const double c = cs_[x], s = sn_[x];
+            V[j * LD + pp_[x]] = c * vp[u] - s * vq[u];
+            V[j * LD + qq_[x]] = s * vp[u] + c * vq[u];
+          }
+        }
       }
       __syncthreads();
     }
@@ -2017,8 +2052,15 @@ hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
   return hipGetLastError();
 }
 hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
-  // Four waves per subject (one wave per subject measured 2x slower).
-  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_polar<KP, 256>), dim3(N), dim3(256), 0, st, a));
+  // Four waves per subject (one wave per subject measured 2x slower).  Above
+  // K padding 80 the Jacobi fallback runs as its own launch of 16 waves per
+  // subject, with G in LDS.
+  SRM_KP_SWITCH(kp, if constexpr (KP <= 80) {
+    hipLaunchKernelGGL((k_polar<KP, 256, POLAR_BOTH>), dim3(N), dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_polar<KP, 256, POLAR_NS>), dim3(N), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_polar<KP, 1024, POLAR_JAC>), dim3(N), dim3(1024), 0, st, a);
+  });
   hipLaunchKernelGGL(k_polar_done, dim3(1), dim3(64), 0, st, a.sc);
   return hipGetLastError();
 }
