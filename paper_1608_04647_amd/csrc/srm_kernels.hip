@@ -3,7 +3,8 @@
 // Data layout in HBM (all row-major, zero padded):
 //   Xhat   : sum_i vp_i rows x ldt columns, one plane (FP32 or BF16) or two
 //            planes (BF16 hi, BF16 lo).  vp_i = round_up(v_i, 32),
-//            ldt = round_up(t, 64).  Subjects are stacked; row r is global.
+//            ldt = round_up(t, 64) (128 for the one-pass sweep).  Subjects
+//            are stacked; row r is global.
 //   A, S   : "records", i.e. the exact per-lane operand layout of the
 //            matrix-core instructions, so a wave loads an operand tile with one
 //            contiguous 1-2 KiB access and never shuffles it.
@@ -18,14 +19,21 @@
 //            lane l holds S[16 jb + l%16][16 tb + 4 (l/16) + s], s = 0..3.
 //
 // Per EM iteration (deferred W: W_i = A_i P_i with P_i = (A_i^T A_i)^-1/2):
-//   k_mphase   A = Xhat S^T                       (Eq. 4 numerator, A_i)
-//   k_ephase   Z_s = A_s^T Xhat_s, G_s = A_s^T A_s per slice (Eq. 10 partials,
-//              Eq. 4 Gram), one streaming pass over Xhat and A
-//   k_polar    G_i -> Jacobi eig (FP64) -> P_i, tr(W_i^T A_i), rho_i^2
+//   k_fused    one-pass sweep (BF16 forms, K padding <= 64, ldt <= 512):
+//              A = Xhat S^T per chunk in LDS, then Z_s = A_s^T Xhat_s and
+//              G_s = A_s^T A_s per slice (Eq. 4 numerator and Gram, Eq. 10
+//              partials); A never goes to HBM
+//   k_mphase   two-pass sweep, pass 1: A = Xhat S^T (Eq. 4 numerator, A_i)
+//   k_ephase   two-pass sweep, pass 2: Z_s and G_s per slice from A
+//   k_gram_z   sample-space variant: Z_i = S G_i and S G_i S^T from
+//              G_i = Xhat_i^T Xhat_i, formed once by k_gram_build
+//   k_polar    G_i -> P_i = G_i^-1/2 (FP64): Newton-Schulz from the previous
+//              P_i, else cyclic Jacobi; tr(W_i^T A_i), rho_i^2 (Eq. 4-5)
 //   k_ereduce  Y = sum_i rho_i^-2 P_i sum_s Z_s   (Eq. 10 reduction, FP64)
 //   k_post_prep rho0, M = (Sigma_s^-1 + rho0 I)^-1, log-det (Eq. 7-8, FP64)
 //   k_post_s   S = M Y (Eq. 10 with Sigma_s [I - rho0 M] = M), S S^T partials
-//   k_post_fin Sigma_s = M + S S^T / t (Eq. 11), tr(Sigma_s), log-likelihood
+//   k_post_sig Sigma_s = M + S S^T / t (Eq. 11)
+//   k_post_fin tr(Sigma_s) (for Eq. 5), log-likelihood
 // All reductions run in a fixed order: results are bitwise reproducible.
 
 #include <hip/hip_runtime.h>
