@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-subjects", type=int, default=8)
+    ap.add_argument("--cpu-subjects", type=int, default=24)
     ap.add_argument("--subjects", type=int, default=0,
                     help="development only: fewer subjects of the same shape")
     ap.add_argument("--no-gram", action="store_true",
