@@ -131,6 +131,21 @@ __device__ double block_sum256(double v, double* red /* >= 4 */) {
   return r;
 }
 
+// Sum over a workgroup of NT threads, in a fixed order.
+template <int NT>
+__device__ double block_sum_nt(double v, double* red /* >= NT / 64 */) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation: demean (Algorithm 1), convert, per-row ||xhat||^2.
 // One wave per (padded) global row.
@@ -853,10 +868,11 @@ __global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense FP64 helpers for k x k matrices (one workgroup of 256 threads),
+// Dense FP64 helpers for k x k matrices (one workgroup of NT threads),
 // in place on one LDS matrix, row-major with leading dimension ld.
 // ---------------------------------------------------------------------------
 // In-place lower Cholesky (right-looking).  Returns false if not PD.
+template <int NT>
 __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
   const int tid = threadIdx.x;
   if (tid == 0) *flag = 0;
@@ -873,10 +889,10 @@ __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
     }
     __syncthreads();
     const double djj = A[j * ld + j];
-    for (int i = j + 1 + tid; i < k; i += 256) A[i * ld + j] /= djj;
+    for (int i = j + 1 + tid; i < k; i += NT) A[i * ld + j] /= djj;
     __syncthreads();
     const int m = k - 1 - j;
-    for (int idx = tid; idx < m * m; idx += 256) {
+    for (int idx = tid; idx < m * m; idx += NT) {
       const int r = j + 1 + idx / m, c = j + 1 + idx % m;
       if (c <= r) A[r * ld + c] -= A[r * ld + j] * A[c * ld + j];
     }
@@ -893,19 +909,20 @@ __device__ bool chol_lower(double* A, int k, int ld, int* flag) {
 // columns c < m and L's columns c >= m.  Pivot row m is used unscaled
 // (1 / L_mm folded into the update) and scaled one step later, when nothing
 // reads it any more.  col: [k] doubles of scratch.
+template <int NT>
 __device__ void tri_inv_lower_inplace(double* A, int k, int ld, double* col) {
   const int tid = threadIdx.x;
   double prev_inv = 0.0;
   for (int m = 0; m < k; ++m) {
     const double inv = 1.0 / A[m * ld + m];
-    for (int r = m + 1 + tid; r < k; r += 256) col[r] = A[r * ld + m];
+    for (int r = m + 1 + tid; r < k; r += NT) col[r] = A[r * ld + m];
     if (m > 0) {  // finish the previous pivot row
-      for (int c = tid; c < m - 1; c += 256) A[(m - 1) * ld + c] *= prev_inv;
+      for (int c = tid; c < m - 1; c += NT) A[(m - 1) * ld + c] *= prev_inv;
       if (tid == 0) A[(m - 1) * ld + m - 1] = prev_inv;
     }
     __syncthreads();
     const int w = m + 1;
-    for (int idx = tid; idx < (k - 1 - m) * w; idx += 256) {
+    for (int idx = tid; idx < (k - 1 - m) * w; idx += NT) {
       const int r = m + 1 + idx / w, c = idx % w;
       const double l = col[r] * inv;
       if (c < m)
@@ -917,7 +934,7 @@ __device__ void tri_inv_lower_inplace(double* A, int k, int ld, double* col) {
     prev_inv = inv;
   }
   if (k > 0) {
-    for (int c = tid; c < k - 1; c += 256) A[(k - 1) * ld + c] *= prev_inv;
+    for (int c = tid; c < k - 1; c += NT) A[(k - 1) * ld + c] *= prev_inv;
     if (tid == 0) A[(k - 1) * ld + k - 1] = prev_inv;
   }
   __syncthreads();
@@ -926,9 +943,10 @@ __device__ void tri_inv_lower_inplace(double* A, int k, int ld, double* col) {
 // In place: lower-triangular X (lower triangle of A) becomes the full
 // symmetric X^T X.  Entries above the diagonal are formed first (that
 // storage is free), the diagonal in diag[k], then mirrored down.
+template <int NT>
 __device__ void ltl_inplace(double* A, int k, int ld, double* diag) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < k * k; idx += 256) {
+  for (int idx = tid; idx < k * k; idx += NT) {
     const int a = idx / k, b = idx % k;
     if (a > b) continue;
     double s = 0.0;
@@ -939,7 +957,7 @@ __device__ void ltl_inplace(double* A, int k, int ld, double* diag) {
       A[a * ld + b] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < k * k; idx += 256) {
+  for (int idx = tid; idx < k * k; idx += NT) {
     const int a = idx / k, b = idx % k;
     if (a > b)
       A[a * ld + b] = A[b * ld + a];
@@ -950,8 +968,9 @@ __device__ void ltl_inplace(double* A, int k, int ld, double* diag) {
 }
 
 // out = X^T X for lower-triangular X (full symmetric result, row-major ldo).
+template <int NT>
 __device__ void ltl(const double* X, int k, int ld, double* out, int ldo) {
-  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+  for (int idx = threadIdx.x; idx < k * k; idx += NT) {
     const int a = idx / k, b = idx % k;
     const int m0 = a > b ? a : b;
     double s = 0.0;
@@ -965,48 +984,50 @@ __device__ void ltl(const double* X, int k, int ld, double* out, int ldo) {
 // Posterior preparation (one workgroup): rho0 (Eq. 8), Cholesky of Sigma_s,
 // Sigma_s^-1, M = (Sigma_s^-1 + rho0 I)^-1 (Eq. 7), log|I + rho0 Sigma_s| and
 // the likelihood's data terms.  One k x k matrix in LDS (up to 132 KB at
-// K padding 128); every factor and inverse is formed in place.
+// K padding 128); every factor and inverse is formed in place, by sixteen
+// waves (the k sequential steps are short; more waves shorten each).
 // ---------------------------------------------------------------------------
 
 template <int KP>
-__global__ __launch_bounds__(256) void k_post_prep(PrepArgs a) {
+__global__ __launch_bounds__(1024) void k_post_prep(PrepArgs a) {
+  constexpr int NT = 1024;
   constexpr int LD = KP + 1;
   __shared__ double A[KP * LD];
   __shared__ double vec[KP];
-  __shared__ double red[4];
+  __shared__ double red[NT / 64];
   __shared__ int flag;
   const int tid = threadIdx.x, k = a.k;
 
   double r0 = 0.0, vl = 0.0, cr = 0.0;
-  for (int i = tid; i < a.N; i += 256) {
+  for (int i = tid; i < a.N; i += NT) {
     const double r = a.rho2[i];
     r0 += 1.0 / r;
     vl += (double)a.subj[i].v * log(r);
     cr += a.c[i] / r;
   }
-  const double rho0 = block_sum256(r0, red);
-  const double svl = block_sum256(vl, red);
-  const double scr = block_sum256(cr, red);
+  const double rho0 = block_sum_nt<NT>(r0, red);
+  const double svl = block_sum_nt<NT>(vl, red);
+  const double scr = block_sum_nt<NT>(cr, red);
 
-  for (int idx = tid; idx < k * k; idx += 256)
+  for (int idx = tid; idx < k * k; idx += NT)
     A[(idx / k) * LD + idx % k] = a.sig[(idx / k) * KP + idx % k];
   __syncthreads();
-  bool ok = chol_lower(A, k, LD, &flag);
+  bool ok = chol_lower<NT>(A, k, LD, &flag);
   double ld1 = 0.0;
-  for (int j = tid; j < k; j += 256) ld1 += 2.0 * log(A[j * LD + j]);
-  ld1 = block_sum256(ld1, red);
-  tri_inv_lower_inplace(A, k, LD, vec);
-  ltl_inplace(A, k, LD, vec);  // A = Sigma_s^-1
-  for (int j = tid; j < k; j += 256) A[j * LD + j] += rho0;
+  for (int j = tid; j < k; j += NT) ld1 += 2.0 * log(A[j * LD + j]);
+  ld1 = block_sum_nt<NT>(ld1, red);
+  tri_inv_lower_inplace<NT>(A, k, LD, vec);
+  ltl_inplace<NT>(A, k, LD, vec);  // A = Sigma_s^-1
+  for (int j = tid; j < k; j += NT) A[j * LD + j] += rho0;
   __syncthreads();
-  ok = chol_lower(A, k, LD, &flag) && ok;
+  ok = chol_lower<NT>(A, k, LD, &flag) && ok;
   double ld2 = 0.0;
-  for (int j = tid; j < k; j += 256) ld2 += 2.0 * log(A[j * LD + j]);
-  ld2 = block_sum256(ld2, red);
-  tri_inv_lower_inplace(A, k, LD, vec);
-  for (int idx = tid; idx < KP * KP; idx += 256) a.M[idx] = 0.0;
+  for (int j = tid; j < k; j += NT) ld2 += 2.0 * log(A[j * LD + j]);
+  ld2 = block_sum_nt<NT>(ld2, red);
+  tri_inv_lower_inplace<NT>(A, k, LD, vec);
+  for (int idx = tid; idx < KP * KP; idx += NT) a.M[idx] = 0.0;
   __syncthreads();
-  ltl(A, k, LD, a.M, KP);
+  ltl<NT>(A, k, LD, a.M, KP);
   if (tid == 0) {
     a.sc->rho0 = rho0;
     a.sc->sum_vlogrho = svl;
@@ -2040,7 +2061,7 @@ hipError_t launch_ereduce(hipStream_t st, int kp, int ncol, int ngrp,
   return hipGetLastError();
 }
 hipError_t launch_post_prep(hipStream_t st, int kp, const PrepArgs& a) {
-  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_post_prep<KP>), dim3(1), dim3(256), 0, st, a));
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_post_prep<KP>), dim3(1), dim3(1024), 0, st, a));
   return hipGetLastError();
 }
 hipError_t launch_post_s(hipStream_t st, int kp, int prec, int nblk,
