@@ -356,7 +356,7 @@ def test_getters_before_first_iteration():
     assert len(g.loglik()) == 1
 
 
-@pytest.mark.parametrize("case", ["tiny", "slices", "ragged", "wide"])
+@pytest.mark.parametrize("case", ["tiny", "slices", "ragged", "wide", "wide2"])
 def test_fused_and_two_pass_sweeps_agree(case):
     """The one-pass sweep (A never stored) and the two-pass sweep (A = Xhat S^T
     written, then A^T Xhat) are the same EM; both meet the BF16 bar against the
