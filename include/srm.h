@@ -146,7 +146,8 @@ srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
 /* Kernel phases of one iteration, in launch order (indices of srm_profile):
  *  SRM_PHASE_MPHASE    A = Xhat S^T over all subjects (Eq. 4, A_i)
  *  SRM_PHASE_EPHASE    per-slice A^T Xhat and A^T A (Eq. 10 partials, Eq. 4 Gram)
- *  SRM_PHASE_POLAR     per-subject FP64 Jacobi polar factor and rho_i^2 (Eq. 4-5)
+ *  SRM_PHASE_POLAR     per-subject FP64 polar factor (Newton-Schulz from the
+ *                      previous one, else Jacobi) and rho_i^2 (Eq. 4-5)
  *  SRM_PHASE_EREDUCE   Y = sum_i rho_i^-2 W_i^T Xhat_i (Eq. 10 reduction)
  *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11)
  *  SRM_PHASE_FUSED     one-pass sweep forming A, A^T Xhat and A^T A together
