@@ -7,8 +7,9 @@ one EM iteration (M-step on the current posterior, then the next E-step)
 over all subjects, replayed as one captured hipGraph; inputs are resident in
 HBM before the timed region starts.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
-GPU (see the sharding notes in the design doc).
+Prints one JSON line.  --gpus N with N > 1 is refused: the sweep is measured
+on one GPU (across GPUs it would shard by subject, with one all-reduce of the
+k x t E-step sum per iteration, which is not implemented).
 """
 from __future__ import annotations
 
@@ -193,7 +194,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding subjects across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
