@@ -65,6 +65,12 @@ CASES = {
     "k100": synth.Workload("k100", 3, 300, 420, 150, 100, 4,
                            sigma_lo=0.5, sigma_hi=2.0, rho_lo=0.3, rho_hi=0.6),
     "k128": synth.Workload("k128", 2, 200, 260, 140, 128, 3, rho_lo=0.3, rho_hi=0.6),
+    # the K paddings at the edges of the polar paths: 80 (the largest held in
+    # LDS) and 96 (the smallest with the separate Jacobi launch)
+    "k80": synth.Workload("k80", 3, 200, 300, 120, 75, 4, sigma_lo=0.5, sigma_hi=2.0,
+                          rho_lo=0.3, rho_hi=0.6),
+    "k96": synth.Workload("k96", 3, 200, 300, 130, 90, 4, sigma_lo=0.5, sigma_hi=2.0,
+                          rho_lo=0.3, rho_hi=0.6),
     # single subject; smallest k
     "n1k1": synth.Workload("n1k1", 1, 40, 40, 16, 1, 5),
     # 500 TRs and k = 50: the batched workload's shape per subject
@@ -98,7 +104,8 @@ def test_parity(case, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2", "bf16"])
-@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "n1k1", "wide",
+@pytest.mark.parametrize("case", ["tiny", "ragged", "slices", "k100", "k128", "k80", "k96",
+                                  "n1k1", "wide",
                                   "vk", "min"])
 def test_sample_space_iteration_parity(case, prec):
     """The sample-space iteration (G_i = Xhat_i^T Xhat_i formed once, then
