@@ -65,6 +65,9 @@ CASES = {
     "k100": synth.Workload("k100", 3, 300, 420, 150, 100, 4,
                            sigma_lo=0.5, sigma_hi=2.0, rho_lo=0.3, rho_hi=0.6),
     "k128": synth.Workload("k128", 2, 200, 260, 140, 128, 3, rho_lo=0.3, rho_hi=0.6),
+    # K padding 48 (three feature blocks) through the one-pass sweep with
+    # four waves (t = 180)
+    "k40": synth.Workload("k40", 3, 150, 400, 180, 40, 4, sigma_lo=0.5, sigma_hi=2.0),
     # the K paddings at the edges of the polar paths: 80 (the largest held in
     # LDS) and 96 (the smallest with the separate Jacobi launch)
     "k80": synth.Workload("k80", 3, 200, 300, 120, 75, 4, sigma_lo=0.5, sigma_hi=2.0,
