@@ -355,6 +355,29 @@ def test_rank_deficient_subject_raises():
     assert ei.value.status == srm.SRM_E_RANK
 
 
+def test_profile_reports_the_sweep_phases():
+    """srm_profile times each phase of the sweep that runs: the one-pass sweep
+    where it applies, M- and E-phase otherwise; its iterations count like
+    srm_fit's and leave the same state as the captured graph."""
+    srm = _srm()
+    w = CASES["wide"]
+    d = synth.generate(w, seed=5)
+    for flags, on, off in ((0, ("fused",), ("mphase", "ephase")),
+                           (srm.SRM_TWO_PASS, ("mphase", "ephase"), ("fused",))):
+        a = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+        b = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], flags=flags)
+        prof = a.profile(2)
+        b.fit(2)
+        for ph in on + ("polar", "ereduce", "posterior"):
+            assert prof[ph] > 0, (flags, ph, prof)
+        for ph in off + ("gram",):
+            assert prof[ph] == 0, (flags, ph, prof)
+        assert a.iterations() == b.iterations() == 2
+        assert np.array_equal(a.S().cpu().numpy(), b.S().cpu().numpy())
+        a.close()
+        b.close()
+
+
 def test_getters_before_first_iteration():
     srm = _srm()
     w = CASES["tiny"]
