@@ -114,9 +114,11 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
     alg = algorithmic(w, v, prec)
     if ph.get("fused", 0.0) > 0.0:  # one-pass sweep: Xhat read once, A never stored
         alg["iter_bytes"] = alg["fused"]["bytes"]
-    if gram:  # per iteration: G_i (t x t FP64) read once, S G_i and S G_i S^T
+    if gram:  # per iteration: G_i (t x t; FP32 for the BF16 forms, FP64 for FP32
+        # storage) read once, S G_i and S G_i S^T
         Nn, t, k = float(len(v)), float(w.t), float(w.k)
-        alg["gram"] = {"bytes": Nn * t * t * 8, "flops": 2.0 * Nn * k * t * t + 2.0 * Nn * k * k * t}
+        gb = 8 if prec == "fp32" else 4
+        alg["gram"] = {"bytes": Nn * t * t * gb, "flops": 2.0 * Nn * k * t * t + 2.0 * Nn * k * k * t}
         alg["iter_bytes"], alg["iter_flops"] = alg["gram"]["bytes"], alg["gram"]["flops"]
     res = {"iters_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "init_s": init_s,
            "hbm_GBps": alg["iter_bytes"] / (dt / steps) / 1e9,
@@ -285,7 +287,7 @@ def main():
                 "iters": n_fit,
                 "sample_space": gram_res["init_s"] + n_fit * gram_res["ms_per_step"] / 1e3,
                 "streamed": head["init_s"] + n_fit * head["ms_per_step"] / 1e3},
-            "k_gram_z_fp64_TFLOPs": ga["flops"] / (gms / 1e3) / 1e12 if gms > 0 else None,
+            "k_gram_z_TFLOPs": ga["flops"] / (gms / 1e3) / 1e12 if gms > 0 else None,
             "k_gram_z_GBps": ga["bytes"] / (gms / 1e3) / 1e9 if gms > 0 else None}
     if check is not None:
         out["error_vs_oracle"] = check

@@ -1851,27 +1851,28 @@ __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
   const int n = lane & 15, g = lane >> 4;
   const int qt = blockIdx.x, i = blockIdx.y;
   const int64_t q0 = 64 * (int64_t)qt;
-  const float* G = a.G + (int64_t)i * a.ldt * a.ldt + q0 + 16 * wave + n;
+  // G_i is stored in full and symmetric: the lane's column q of G_i is read
+  // as row q, four TRs per 16-byte load.
+  const float* Gq = a.G + (int64_t)i * a.ldt * a.ldt + (q0 + 16 * wave + n) * a.ldt;
   f32x4 acc[NB];
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) acc[jb] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int64_t p0 = 0; p0 < a.t; p0 += PC) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < KP * PC; idx += 256) {
-      const int j = idx / PC, pp = idx % PC;
-      Ss[j][pp] = (j < a.k && p0 + pp < a.t) ? (float)a.S[(int64_t)j * a.ldt + p0 + pp] : 0.f;
+    for (int idx = threadIdx.x; idx < KP * PC / 2; idx += 256) {  // two TRs per load
+      const int j = idx / (PC / 2), pp = 2 * (idx % (PC / 2));
+      double2 v = make_double2(0.0, 0.0);
+      if (j < a.k) v = *(const double2*)&a.S[(int64_t)j * a.ldt + p0 + pp];
+      Ss[j][pp] = p0 + pp < a.t ? (float)v.x : 0.f;
+      Ss[j][pp + 1] = p0 + pp + 1 < a.t ? (float)v.y : 0.f;
     }
     __syncthreads();
     // K-step of 16 TRs: lane group g takes TRs 4 g .. 4 g + 3 (one per
     // product), for both operands alike.
 #pragma unroll 2
     for (int ps = 0; ps < PC; ps += 16) {
-      float gv[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t p = p0 + ps + 4 * g + e;  // < ldt: chunks end at ldt
-        gv[e] = G[p * a.ldt];
-      }
+      const float4 g4 = *(const float4*)(Gq + p0 + ps + 4 * g);  // < ldt: chunks end at ldt
+      const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) {
         const float4 sv = *(const float4*)&Ss[16 * jb + n][ps + 4 * g];
