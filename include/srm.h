@@ -19,7 +19,8 @@
  * log-likelihood; the printed Eq. 5 is garbled (a missing 1/(T V) factor and
  * the total V where v_i belongs).  The factor 1/2 printed in A_i is dropped
  * (the polar factor is scale invariant).  Sigma_s starts at I, rho_i^2 at 1,
- * and W_i at the caller's orthonormal W0_i.  The log-likelihood reported per
+ * and W_i at the caller's orthonormal W0_i or a seeded random orthonormal map
+ * the library draws (srm_init).  The log-likelihood reported per
  * iteration is the marginal Gaussian log-density of the demeaned data under
  * the parameters entering that iteration, reduced with the inversion lemma
  * (Eq. 7) and Eq. 8.
@@ -78,9 +79,11 @@ enum {
   SRM_TWO_PASS = 4u,    /* use the two-pass sweep (A = Xhat S^T to HBM, then
                            A^T Xhat) even where the fused one-pass sweep applies
                            (BF16 forms with k <= 64 and t <= 512)              */
-  SRM_X_HOST = 8u,      /* srm_init's X[i] are host pointers: each subject is
-                           uploaded through a staging area in the workspace and
-                           converted there (no full FP32 copy on the device)  */
+  SRM_X_HOST = 8u,      /* the X[i] of srm_init and X_i of srm_ingest are host
+                           pointers: each subject is uploaded in chunks through
+                           two staging buffers in the workspace on a second
+                           stream and converted there (no full FP32 copy on
+                           the device)                                        */
   SRM_ZSCORE = 16u,     /* standardise each voxel (the z-score preprocessing of
                            the paper's implementation, Sec. IV-A): after the
                            mean, divide by the population standard deviation
@@ -116,31 +119,79 @@ srm_status srm_workspace_size(const srm_desc *desc, size_t *bytes);
 
 /* Algorithm 1, initialisation: demean each X_i (mu_i = row means over t),
  * store Xhat_i in desc->prec inside the workspace, compute c_i = ||Xhat_i||^2
- * from the stored values, set W_i = W0_i, rho_i^2 = 1, Sigma_s = I, and run
- * the first E-step (its log-likelihood is the first one srm_fit reports).
+ * from the stored values, set the starting maps W_i, rho_i^2 = 1,
+ * Sigma_s = I, and run the first E-step (its log-likelihood is the first one
+ * srm_fit reports).  Equivalent to srm_init_begin, srm_ingest of every
+ * subject in order, and srm_init_end.
  *   X:  host array of N device pointers (host pointers with SRM_X_HOST);
  *       X[i] is v_i x t float32, row stride t.  Read during the call only
  *       (the caller keeps ownership).
- *   W0: host array of N host pointers; W0[i] is v_i x k float64 with
- *       orthonormal columns (checked: max|W0^T W0 - I| <= 1e-8 unless
- *       SRM_NO_W0_CHECK).  Read during the call only.
+ *   W0: NULL, or a host array of N host pointers; W0[i] is v_i x k float64
+ *       with orthonormal columns (checked: max|W0^T W0 - I| <= 1e-8 unless
+ *       SRM_NO_W0_CHECK), read during the call only.  Where W0 or W0[i] is
+ *       NULL the library draws subject i's start itself: Algorithm 1's random
+ *       orthonormal start, taken as the polar factor G (G^T G)^-1/2 of a
+ *       v_i x k matrix G of N(0, 1) entries, which is Haar distributed.  Entry
+ *       e = r k + c of G is normal number e % 4 of the Philox4x64-10 block
+ *       (Salmon et al., SC 2011) with counter (e / 4, i, 0, 0) and key
+ *       (seed, 0), by the Box-Muller transform of the block's 64-bit words
+ *       x taken as u = (floor(x / 2^11) + 1/2) 2^-53: words 0, 1 give
+ *       sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1), words 2, 3 likewise.
+ *   seed: Philox key word 0 for the drawn starts (unused when every W0[i]
+ *       is given).
  *   workspace: device memory of at least srm_workspace_size bytes, 256-byte
  *       aligned, owned by the caller, used exclusively by this context.
- * Errors: SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_NONFINITE, SRM_E_HIP, SRM_E_NOTPD.
- * On success *out is a new context (free with srm_free). */
+ * Errors: SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_NONFINITE, SRM_E_HIP, SRM_E_NOTPD,
+ * SRM_E_RANK (a drawn start or a W0 whose polar factor does not exist).
+ * On success *out is a new context (free with srm_free); on failure none. */
 srm_status srm_init(srm_ctx **out, const srm_desc *desc, const float *const *X,
-                    const double *const *W0, void *workspace, size_t ws_bytes);
+                    const double *const *W0, uint64_t seed, void *workspace,
+                    size_t ws_bytes);
+
+/* Incremental initialisation, for data that should not be held in memory all
+ * at once (the per-subject loading of the paper's implementation, Sec. IV-B).
+ *  srm_init_begin: validates the descriptor and workspace and returns a
+ *      context awaiting its subjects (the same arguments as srm_init, without
+ *      the data).  Only srm_ingest, srm_init_end, srm_get_info and srm_free
+ *      are valid on it until srm_init_end succeeds (SRM_E_STATE otherwise).
+ *  srm_ingest: demeans, converts and stores subject i (any order, once each).
+ *      X_i: v_i x t float32, row stride t; a device pointer, or a host pointer
+ *      with SRM_X_HOST, in which case the rows are uploaded in chunks through
+ *      two staging buffers of the workspace on a second stream, each chunk's
+ *      upload overlapping the conversion of the previous one.  W0_i: v_i x k
+ *      float64 host map with orthonormal columns, or NULL to draw subject i's
+ *      start as described under srm_init.  Both are read during the call only:
+ *      the caller may free or reuse them when it returns.
+ *      Errors: SRM_E_ARG (index, NULL X_i, repeated subject, W0_i not
+ *      orthonormal), SRM_E_STATE (after srm_init_end), SRM_E_HIP.  A failed
+ *      call leaves subject i not ingested.
+ *  srm_init_end: checks that every subject was ingested (SRM_E_STATE
+ *      otherwise), rejects NaN or Inf data (SRM_E_NONFINITE), forms G_i with
+ *      SRM_GRAM, and runs the first E-step (SRM_E_RANK, SRM_E_NOTPD).  On any
+ *      failure the context stays unusable and must be freed. */
+srm_status srm_init_begin(srm_ctx **out, const srm_desc *desc, uint64_t seed,
+                          void *workspace, size_t ws_bytes);
+srm_status srm_ingest(srm_ctx *ctx, int32_t i, const float *X_i, const double *W0_i);
+srm_status srm_init_end(srm_ctx *ctx);
 
 /* One EM iteration of Algorithm 1 (M-step on the current posterior, then the
  * next E-step).  loglik (host, nullable) receives the log-likelihood of the
  * parameters entering the iteration.  Synchronises the stream.
- * Errors: SRM_E_RANK, SRM_E_NOTPD, SRM_E_HIP. */
+ * Errors as srm_fit. */
 srm_status srm_em_step(srm_ctx *ctx, double *loglik);
 
 /* n_iter >= 0 EM iterations (fixed count; the paper's stopping criterion is
  * unspecified).  loglik (host [n_iter], nullable) receives the log-likelihood
  * of the parameters entering each iteration.  The iterations are enqueued
- * without host synchronisation; the stream is synchronised once at the end. */
+ * without host synchronisation (one captured hipGraph replayed per iteration
+ * unless SRM_NO_GRAPH; srm_get_info says which ran); the stream is
+ * synchronised once at the end.
+ * Errors: SRM_E_RANK (some A_i^T A_i numerically singular, reading of the
+ * polar factor's existence), SRM_E_NOTPD, SRM_E_HIP, SRM_E_STATE.  On
+ * SRM_E_RANK or SRM_E_NOTPD the iteration that failed and every later one in
+ * the call stop at their first kernel, and the carried state (everything
+ * srm_get_state returns, the iteration count included) is put back to what
+ * it was when the call started. */
 srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
 
 /* Kernel phases of one iteration, in launch order (indices of srm_profile):
@@ -167,7 +218,8 @@ enum {
 /* Runs n_iter iterations like srm_fit but with direct kernel launches, each
  * kernel bracketed by HIP events on the context's stream, and adds each
  * phase's measured milliseconds into ms[SRM_NPHASE] (host; zeroed first).
- * Synchronises after every iteration; meant for measurement, not speed. */
+ * Synchronises after every iteration; meant for measurement, not speed.
+ * Errors and their undoing as srm_fit. */
 srm_status srm_profile(srm_ctx *ctx, int32_t n_iter, double *ms);
 
 /* Project new samples of subject i into the shared space (Sec. II-A:
@@ -218,8 +270,9 @@ srm_status srm_get_loglik(srm_ctx *ctx, double *dst, int32_t capacity,
  * log-likelihood history and the iteration count (Algorithm 1 carries exactly
  * these from one iteration to the next; the data enter through Xhat_i only).
  *  srm_get_state: host blob; with blob == NULL, *bytes receives the size.
- *                 Otherwise *bytes must hold at least that size.  SRM_E_STATE
- *                 before the first iteration.  Synchronises the stream.
+ *                 Otherwise *bytes must hold at least that size.  Valid from
+ *                 srm_init_end on (a blob taken before the first iteration
+ *                 resumes from the first E-step).  Synchronises the stream.
  *  srm_set_state: host blob from srm_get_state of a context with the same
  *                 descriptor (N, v, t, k, format, sweep) and the same data
  *                 (checked through c_i = ||Xhat_i||_F^2, bitwise): SRM_E_ARG
@@ -230,6 +283,27 @@ srm_status srm_set_state(srm_ctx *ctx, const void *blob, size_t bytes);
 
 /* Number of completed iterations. */
 srm_status srm_iterations(const srm_ctx *ctx, int32_t *n);
+
+/* How the context runs its iterations (no device work; valid from
+ * srm_init_begin on). */
+enum {
+  SRM_SWEEP_ONE_PASS = 0, /* A = Xhat S^T, A^T Xhat and A^T A in one pass over Xhat */
+  SRM_SWEEP_TWO_PASS = 1, /* A to HBM, then A^T Xhat and A^T A              */
+  SRM_SWEEP_GRAM = 2      /* sample-space products on G_i (SRM_GRAM)         */
+};
+typedef struct {
+  int32_t sweep;          /* SRM_SWEEP_*                                          */
+  int32_t graph;          /* 1: the last srm_fit replayed one captured hipGraph
+                             per iteration; 0: direct launches (SRM_NO_GRAPH, a
+                             failed capture, or no srm_fit yet)                */
+  int32_t k_padded;       /* k rounded up to the matrix-core tile (16)           */
+  int32_t n_ranges;       /* workgroups of the streaming sweep (equal row ranges) */
+  int32_t n_slices;       /* row ranges split at subject boundaries              */
+  int32_t reserved[3];
+  int64_t ldt;            /* stored row stride of Xhat (t padded)               */
+  size_t workspace_bytes; /* = srm_workspace_size                                */
+} srm_info;
+srm_status srm_get_info(const srm_ctx *ctx, srm_info *info);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *srm_last_error(void);

@@ -6,5 +6,7 @@ with it.
 """
 from .srm_oracle import (  # noqa: F401
     OracleRankError, OracleNotPD, demean, zscore, posterior, loglik, polar_svd,
-    m_step_subject, em_fit, naive_estep, fit_gram, flop_model,
+    m_step_subject, em_fit, naive_estep, fit_gram, gram_summary,
+    fit_gram_summaries, w_of, philox4x64, seeded_gaussian,
+    seeded_start,
 )

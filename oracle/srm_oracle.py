@@ -44,12 +44,14 @@ Pins (tests/test_oracle.py): naive V x V E-step (Eq. 2-3), the closed form
 Sigma_s (I - rho0 M) = M, orthonormality, polar = SVD, the trace identity,
 monotone log-likelihood, the N = 1 PPCA closed form, M-step = argmax of the
 expected complete-data log-likelihood, planted recovery, rotation
-equivariance, agreement with the t x t Gram form.
+equivariance, agreement with the t x t Gram form (list and streamed input
+alike), the Philox generator against NumPy's implementation of the same
+published generator, and the Haar start's orthonormality.
 """
 from __future__ import annotations
 
 import math
-from typing import List, Optional, Sequence
+from typing import Callable, Iterable, List, Optional, Sequence
 
 import numpy as np
 import scipy.linalg as sla
@@ -238,30 +240,42 @@ def naive_estep(Xh: List[np.ndarray], W: List[np.ndarray], rho2: np.ndarray,
     return ES, Ess, ll, cov
 
 
-def fit_gram(X: List[np.ndarray], k: int, n_iter: int, W0: List[np.ndarray]):
+def gram_summary(Xi: np.ndarray, W0i: np.ndarray, demeaned: bool = False):
+    """What one pass over subject i's data leaves for the t x t Gram form:
+    (G_i = Xhat_i^T Xhat_i, c_i = ||Xhat_i||_F^2, v_i, W0_i^T Xhat_i).
+    demeaned=True takes X_i as Xhat_i, as in em_fit."""
+    if demeaned:
+        xh = np.asarray(Xi, dtype=np.float64)
+        ci = float(np.sum(xh * xh))
+    else:
+        _, xh, ci = demean(Xi)
+    return xh.T @ xh, ci, xh.shape[0], np.asarray(W0i, dtype=np.float64).T @ xh
+
+
+def fit_gram_summaries(summ: Iterable, k: int, n_iter: int, final_loglik: bool = False):
     """The same EM written on the t x t Gram G_i = Xhat_i^T Xhat_i.
 
     Exact algebra on Eq. 4, 10 and R1: with A_i = Xhat_i S^T,
     W_i^T Xhat_i = P_i S G_i and A_i^T A_i = S G_i S^T, where
-    P_i = (A_i^T A_i)^-1/2 (eigh).  One pass over the data builds G_i, c_i and
-    W0_i^T Xhat_i; W_i = Xhat_i S^T P_i is formed only at the end."""
-    N = len(X)
-    t = X[0].shape[1]
-    G, c, v, Z0 = [], [], [], []
-    for Xi, w0 in zip(X, W0):
-        _, xh, ci = demean(Xi)
-        G.append(xh.T @ xh)
+    P_i = (A_i^T A_i)^-1/2 (eigh).  summ yields gram_summary() of every
+    subject, in order; W_i = Xhat_i S^T P_i is left to the caller (w_of)."""
+    G, c, v, Z = [], [], [], []
+    for Gi, ci, vi, Z0i in summ:
+        G.append(Gi)
         c.append(ci)
-        v.append(xh.shape[0])
-        Z0.append(w0.T @ xh)
+        v.append(vi)
+        Z.append(Z0i)  # W_i^T Xhat_i for W_i = W0_i
+    N = len(G)
+    t = G[0].shape[0]
     rho2 = np.ones(N)
     Sigma_s = np.eye(k)
-    Z = Z0  # W_i^T Xhat_i for the current W_i
     ll = []
     P = [None] * N
     S = None
     for _ in range(n_iter):
-        Y = sum((1.0 / rho2[i]) * Z[i] for i in range(N))
+        Y = np.zeros((k, t))
+        for i in range(N):
+            Y += (1.0 / rho2[i]) * Z[i]
         S, M, rho0 = posterior(Y, rho2, Sigma_s)
         ll.append(loglik(c, v, t, rho2, Sigma_s, Y, M, rho0))
         Sigma_s = M + (S @ S.T) / t
@@ -279,19 +293,109 @@ def fit_gram(X: List[np.ndarray], k: int, n_iter: int, W0: List[np.ndarray]):
             newr[i] = (c[i] - 2.0 * tr_wa + t * tau) / (t * v[i])
             Z[i] = P[i] @ SG
         rho2 = newr
-    W = []
-    for Xi, Pi in zip(X, P):
+    out = {"S": S, "rho2": rho2, "Sigma_s": Sigma_s, "ll": ll, "c": np.array(c),
+           "v": v, "t": t, "P": P}
+    if final_loglik:
+        Y = np.zeros((k, t))
+        for i in range(N):
+            Y += (1.0 / rho2[i]) * Z[i]
+        _, M, rho0 = posterior(Y, rho2, Sigma_s)
+        out["ll_final"] = loglik(c, v, t, rho2, Sigma_s, Y, M, rho0)
+    return out
+
+
+def w_of(fit: dict, i: int, Xi: np.ndarray, demeaned: bool = False) -> np.ndarray:
+    """W_i = A_i P_i = Xhat_i S^T P_i of a Gram-form fit (Eq. 4)."""
+    if demeaned:
+        xh = np.asarray(Xi, dtype=np.float64)
+    else:
         _, xh, _ = demean(Xi)
-        W.append(xh @ S.T @ Pi)
-    return {"W": W, "S": S, "rho2": rho2, "Sigma_s": Sigma_s, "ll": ll}
+    return xh @ fit["S"].T @ fit["P"][i]
 
 
-def flop_model(v: Sequence[int], t: int, k: int) -> float:
-    """Per-iteration flop count of Sec. V-A: per subject two V_i x T x K
-    products, one V_i x K x K product and an economy SVD counted as Householder
-    QR (2 m n^2 - 2/3 n^3)."""
-    tot = 0.0
-    for vi in v:
-        tot += 2 * (2.0 * vi * t * k) + 2.0 * vi * k * k \
-            + (2.0 * vi * k * k - 2.0 / 3.0 * k ** 3)
-    return tot
+def fit_gram(X, k: int, n_iter: int, W0, final_loglik: bool = False,
+             demeaned: bool = False):
+    """fit_gram_summaries over lists (or iterables, read once) of X_i and W0_i;
+    with X a sequence, W holds every W_i."""
+    out = fit_gram_summaries((gram_summary(x, w, demeaned) for x, w in zip(X, W0)),
+                             k, n_iter, final_loglik)
+    if isinstance(X, Sequence):
+        out["W"] = [w_of(out, i, X[i], demeaned) for i in range(len(X))]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The random orthonormal start of Algorithm 1 when the library draws it.
+#
+# Algorithm 1 initialises each W_i with "a random orthogonal matrix" without
+# saying how (reading R4).  When the caller passes no W0, the library and this
+# oracle draw the same one: the polar factor G (G^T G)^-1/2 of a v_i x k matrix
+# G of independent N(0, 1) entries, which is Haar distributed on the matrices
+# with orthonormal columns (the distribution of G is invariant under
+# G -> Q G for orthogonal Q, and polar(Q G) = Q polar(G)).  The Gaussian
+# entries come from the counter-based generator Philox4x64-10 (Salmon, Moraes,
+# Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC 2011) and the
+# Box-Muller transform; both sides implement them from those definitions and
+# share no code.
+#
+# Element e = r k + b of subject i's G (row-major) is normal number e % 4 of
+# the Philox block with counter (e // 4, i, 0, 0) and key (seed, 0): the block's
+# 64-bit outputs x0..x3 give u_j = (floor(x_j / 2^11) + 1/2) 2^-53 and
+#   z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1),
+#   z2 = sqrt(-2 ln u2) cos(2 pi u3), z3 = sqrt(-2 ln u2) sin(2 pi u3).
+# ---------------------------------------------------------------------------
+
+_PHILOX_M = (np.uint64(0xD2E7470EE14C6C93), np.uint64(0xCA5A826395121157))
+_PHILOX_W = (np.uint64(0x9E3779B97F4A7C15), np.uint64(0xBB67AE8584CAA73B))
+_LO32 = np.uint64(0xFFFFFFFF)
+_S32 = np.uint64(32)
+
+
+def _mulhilo64(a: np.uint64, b: np.ndarray):
+    """High and low 64-bit words of the 128-bit product a * b (elementwise)."""
+    b = np.asarray(b, dtype=np.uint64)
+    lo = a * b
+    a0, a1 = a & _LO32, a >> _S32
+    b0, b1 = b & _LO32, b >> _S32
+    mid = a1 * b0 + ((a0 * b0) >> _S32)
+    mid2 = (mid & _LO32) + a0 * b1
+    hi = a1 * b1 + (mid >> _S32) + (mid2 >> _S32)
+    return hi, lo
+
+
+def philox4x64(counter, key):
+    """Philox4x64-10: counter = 4 arrays of uint64 words (word 0 least
+    significant), key = 2 uint64 words.  Returns the 4 output words."""
+    c = [np.asarray(x, dtype=np.uint64) for x in counter]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    with np.errstate(over="ignore"):
+        for _ in range(10):
+            hi0, lo0 = _mulhilo64(_PHILOX_M[0], c[0])
+            hi1, lo1 = _mulhilo64(_PHILOX_M[1], c[2])
+            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+            k0 = k0 + _PHILOX_W[0]
+            k1 = k1 + _PHILOX_W[1]
+    return c
+
+
+def seeded_gaussian(v: int, k: int, seed: int, i: int) -> np.ndarray:
+    """Subject i's v x k matrix of N(0, 1) entries (layout above)."""
+    n = v * k
+    nb = (n + 3) // 4
+    b = np.arange(nb, dtype=np.uint64)
+    zero = np.zeros(nb, dtype=np.uint64)
+    x = philox4x64([b, np.full(nb, i, dtype=np.uint64), zero, zero],
+                   (np.uint64(seed), np.uint64(0)))
+    u = [((xj >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for xj in x]
+    r0 = np.sqrt(-2.0 * np.log(u[0]))
+    r2 = np.sqrt(-2.0 * np.log(u[2]))
+    z = np.stack([r0 * np.cos(2.0 * np.pi * u[1]), r0 * np.sin(2.0 * np.pi * u[1]),
+                  r2 * np.cos(2.0 * np.pi * u[3]), r2 * np.sin(2.0 * np.pi * u[3])], axis=1)
+    return z.reshape(-1)[:n].reshape(v, k)
+
+
+def seeded_start(v: int, k: int, seed: int, i: int) -> np.ndarray:
+    """W0_i = polar factor (Eq. 4's map, here applied to a Gaussian) of
+    seeded_gaussian(v, k, seed, i): the library's start when no W0 is given."""
+    W, _ = polar_svd(seeded_gaussian(v, k, seed, i))
+    return W

@@ -1,6 +1,9 @@
 // Host side of the SRM C-ABI: argument validation, work planning, workspace
-// layout, W0 upload, kernel sequencing and hipGraph replay of one iteration.
-// The EM arithmetic itself runs in the kernels of srm_kernels.hip.
+// layout, ingestion of the data (one subject at a time, the upload of the next
+// chunk overlapping the conversion of the last one), the starting maps,
+// kernel sequencing, hipGraph replay of one iteration, and the snapshot that
+// undoes a failed fit.  The EM arithmetic itself runs in the kernels of
+// srm_kernels.hip.
 
 #include <hip/hip_runtime.h>
 
@@ -20,6 +23,7 @@
 namespace srm {
 hipError_t launch_convert(hipStream_t, int, const ConvertArgs&);
 hipError_t launch_rowsum(hipStream_t, int, const double*, const Subject*, double*);
+hipError_t launch_seed(hipStream_t, int, const SeedArgs&);
 hipError_t launch_mphase(hipStream_t, int, int, int, const MArgs&);
 hipError_t launch_ephase(hipStream_t, int, int, int, const EArgs&);
 hipError_t launch_ereduce(hipStream_t, int, int, int, const RArgs&);
@@ -72,6 +76,9 @@ constexpr int kEphaseWGs = 512;
 // Fused sweep: 8-wave workgroups, about one per CU; two equal rounds.
 constexpr int kFusedWGs = 512;
 constexpr int kReduceWGs = 512;
+// Streamed host ingestion: each of the two device staging buffers holds up to
+// this many bytes of one subject's FP32 rows.
+constexpr size_t kStageBytes = (size_t)64 << 20;
 
 struct Plan {
   int N = 0, k = 0, KP = 0, NB = 0, prec = 0;
@@ -82,6 +89,7 @@ struct Plan {
   int nq = 0;         // 64-TR column tiles of G_i
   int rct = 0, ncol_r = 0, gsub = 0, ngrp = 0;
   int nblk_s = 0;
+  int64_t stage_rows = 0;  // rows per staging buffer (streamed host ingestion)
   std::vector<Subject> subj;
   std::vector<Slice> slices;
   std::vector<int32_t> range_slice;
@@ -91,9 +99,10 @@ struct Plan {
          o_s64cur = 0, o_s64new = 0, o_sreccur = 0, o_srecnew = 0,
          o_sspart = 0, o_trpart = 0, o_sigcur = 0, o_signew = 0, o_M = 0,
          o_polwork = 0, o_vprev = 0, o_pjac = 0, o_sc = 0, o_ll = 0, o_subj = 0,
-         o_slices = 0, o_rs = 0, o_srow0 = 0, o_sv = 0, o_xptr = 0, o_stage = 0,
+         o_slices = 0, o_rs = 0, o_stage = 0, o_backup = 0,
          o_G = 0, o_gz = 0, o_subjg = 0;
-  size_t stage_bytes = 0;
+  size_t stage_bytes = 0;  // one staging buffer
+  size_t backup_bytes = 0;
   size_t total = 0;
   size_t arec_bytes = 0, srec_bytes = 0, zpart_bytes = 0;
 };
@@ -119,6 +128,10 @@ srm_status validate(const srm_desc* d) {
   }
   return SRM_OK;
 }
+
+// Workspace regions carried from one iteration to the next (checkpointed,
+// and snapshotted so that a failed fit can be undone).
+std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p);
 
 srm_status make_plan(const srm_desc* d, Plan& p) {
   srm_status s = validate(d);
@@ -173,8 +186,8 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.range_slice[p.nranges] = (int32_t)p.slices.size();
   p.nslices = (int)p.slices.size();
   for (auto& su : p.subj) { su.s_beg = 0; su.s_end = 0; }
-  for (int s = p.nslices - 1; s >= 0; --s) p.subj[p.slices[s].subj].s_beg = s;
-  for (int s = 0; s < p.nslices; ++s) p.subj[p.slices[s].subj].s_end = s + 1;
+  for (int s2 = p.nslices - 1; s2 >= 0; --s2) p.subj[p.slices[s2].subj].s_beg = s2;
+  for (int s2 = 0; s2 < p.nslices; ++s2) p.subj[p.slices[s2].subj].s_end = s2 + 1;
   // reduction geometry
   p.rct = ereduce_ct(p.KP);
   p.ncol_r = (int)(p.ldt / p.rct);
@@ -223,9 +236,6 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_subj = take(sizeof(Subject) * p.N);
   p.o_slices = take(sizeof(Slice) * p.nslices);
   p.o_rs = take(sizeof(int32_t) * (p.nranges + 1));
-  p.o_srow0 = take(sizeof(int64_t) * p.N);
-  p.o_sv = take(sizeof(int32_t) * p.N);
-  p.o_xptr = take(sizeof(void*) * p.N);
   if (p.gram) {
     p.nq = (int)(p.ldt / 64);
     if ((int64_t)p.nq * (p.nq + 1) / 2 * p.N >= ((int64_t)1 << 31))
@@ -235,14 +245,29 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
     p.o_gz = take((size_t)p.N * p.nq * p.KP * p.KP * 8);
     p.o_subjg = take(sizeof(Subject) * p.N);
   }
-  if (d->flags & SRM_X_HOST) {  // staging for one subject's FP32 rows at a time
+  if (d->flags & SRM_X_HOST) {  // two staging buffers for FP32 rows of one subject
     int64_t vmax = 0;
     for (int i = 0; i < p.N; ++i) vmax = std::max<int64_t>(vmax, d->v[i]);
-    p.stage_bytes = (size_t)vmax * p.t * sizeof(float);
-    p.o_stage = take(p.stage_bytes);
+    const int64_t row_bytes = p.t * (int64_t)sizeof(float);
+    p.stage_rows = std::max<int64_t>(1, std::min<int64_t>(vmax, (int64_t)kStageBytes / row_bytes));
+    p.stage_bytes = (size_t)(p.stage_rows * row_bytes);
+    p.o_stage = take(2 * p.stage_bytes);
   }
+  p.backup_bytes = 0;
+  for (const auto& r : state_regions(p)) p.backup_bytes += r.second;
+  p.o_backup = take(p.backup_bytes);
   p.total = off;
   return SRM_OK;
+}
+
+std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p) {
+  const size_t kk = (size_t)p.KP * p.KP * 8;
+  return {{p.o_s64cur, (size_t)p.KP * p.ldt * 8}, {p.o_s64new, (size_t)p.KP * p.ldt * 8},
+          {p.o_sreccur, p.srec_bytes},            {p.o_srecnew, p.srec_bytes},
+          {p.o_sigcur, kk},                       {p.o_signew, kk},
+          {p.o_M, kk},                            {p.o_rho2, sizeof(double) * p.N},
+          {p.o_p64, (size_t)p.N * kk},            {p.o_vprev, (size_t)p.N * kk},
+          {p.o_sc, sizeof(Scalars)},              {p.o_ll, sizeof(double) * kLLCapacity}};
 }
 
 }  // namespace
@@ -250,14 +275,24 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
 struct srm_ctx {
   Plan p;
   uint32_t flags = 0;
-  hipStream_t stream = nullptr;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;   // every kernel
+  hipStream_t cstream = nullptr;  // uploads of streamed host ingestion
   bool own_stream = false;
+  hipEvent_t ev_up[2] = {};       // staging buffer b filled (copy stream)
+  hipEvent_t ev_conv[2] = {};     // staging buffer b converted (compute stream)
+  int64_t stage_seq = 0;          // staging buffers used so far
   char* ws = nullptr;
   int m_grid = 0;
   int64_t m_tpw = 0, m_ntiles = 0;
   int iters = 0;
+  bool ready = false;             // srm_init_end completed
+  bool w0_checked = false;        // srm_init checked every W0_i before ingesting
+  std::vector<char> ingested;     // per subject, between init_begin and init_end
+  std::vector<char> seeded;       // per subject: start drawn by the library
   bool graph_ok = false;
-  bool a_valid = true;  // A records in HBM match the current S (two-pass)
+  bool graph_used = false;        // the last srm_fit replayed the captured graph
+  bool a_valid = true;            // A records in HBM match the current S (two-pass)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // Per-kernel HIP events for srm_profile (direct launches only).
@@ -307,80 +342,69 @@ void parallel_for(int n, F f) {
   for (auto& x : th) x.join();
 }
 
-srm_status check_w0(const Plan& p, const double* const* W0) {
-  std::vector<double> err(p.N, 0.0);
-  parallel_for(p.N, [&](int i) {
-    const int v = p.subj[i].v, k = p.k;
-    std::vector<double> g((size_t)k * k, 0.0);
-    const double* w = W0[i];
-    for (int r = 0; r < v; ++r) {
+// max |W0^T W0 - I| of one subject's v x k map, over row blocks in parallel.
+double w0_error(const double* w, int v, int k) {
+  const int nt = std::max(1, std::min(n_threads(), v / 4096 + 1));
+  std::vector<std::vector<double>> part(nt, std::vector<double>((size_t)k * k, 0.0));
+  parallel_for(nt, [&](int t) {
+    double* g = part[t].data();
+    for (int r = (int)((int64_t)v * t / nt); r < (int)((int64_t)v * (t + 1) / nt); ++r) {
       const double* row = w + (size_t)r * k;
       for (int a = 0; a < k; ++a) {
         const double x = row[a];
-        double* ga = g.data() + (size_t)a * k;
+        double* ga = g + (size_t)a * k;
         for (int b = a; b < k; ++b) ga[b] += x * row[b];
       }
     }
-    double m = 0.0;
-    for (int a = 0; a < k; ++a)
-      for (int b = a; b < k; ++b)
-        m = std::max(m, std::fabs(g[(size_t)a * k + b] - (a == b ? 1.0 : 0.0)));
-    err[i] = m;
   });
-  for (int i = 0; i < p.N; ++i)
-    if (!(err[i] <= 1e-8))
-      return fail(SRM_E_ARG, "W0[%d] is not orthonormal (max|W^T W - I| = %g)", i, err[i]);
-  return SRM_OK;
+  double m = 0.0;
+  for (int a = 0; a < k; ++a)
+    for (int b = a; b < k; ++b) {
+      double s = 0.0;
+      for (int t = 0; t < nt; ++t) s += part[t][(size_t)a * k + b];
+      m = std::max(m, std::fabs(s - (a == b ? 1.0 : 0.0)));
+    }
+  return m;
 }
 
-// W0 -> A records (A = W0, deferred polar factor P = I) and upload.
-srm_status upload_w0(srm_ctx* c, const double* const* W0) {
+// W0_i -> subject i's A records (A = W0, deferred polar factor P = I).
+srm_status upload_w0(srm_ctx* c, int i, const double* W0) {
   const Plan& p = c->p;
-  std::vector<srm_status> st(p.N, SRM_OK);
-  std::vector<std::string> msg(p.N);
-  const int nt = std::min(p.N, n_threads());
-  std::vector<std::thread> th;
-  for (int w = 0; w < nt; ++w) {
-    th.emplace_back([&, w] {
-      std::vector<char> buf;
-      for (int i = w; i < p.N; i += nt) {
-        const Subject& su = p.subj[i];
-        const size_t nrec_el = (size_t)su.vp * p.KP;  // elements in its records
-        const size_t base = arec_index(p.NB, su.row0, 0);
-        if (p.prec == SRM_FP32) {
-          buf.assign(nrec_el * 4, 0);
-          float* f = reinterpret_cast<float*>(buf.data());
-          for (int r = 0; r < su.v; ++r)
-            for (int b = 0; b < p.k; ++b)
-              f[arec_index(p.NB, su.row0 + r, b) - base] = (float)W0[i][(size_t)r * p.k + b];
-          if (hipMemcpy(c->ws + p.o_arec + base * 4, buf.data(), nrec_el * 4,
-                        hipMemcpyHostToDevice) != hipSuccess)
-            st[i] = SRM_E_HIP;
-        } else {
-          buf.assign(nrec_el * 4, 0);
-          uint16_t* hi = reinterpret_cast<uint16_t*>(buf.data());
-          uint16_t* lo = hi + nrec_el;
-          for (int r = 0; r < su.v; ++r)
-            for (int b = 0; b < p.k; ++b) {
-              const float f = (float)W0[i][(size_t)r * p.k + b];
-              const uint16_t h = host_f2bf(f);
-              const size_t o = arec_index(p.NB, su.row0 + r, b) - base;
-              hi[o] = h;
-              lo[o] = host_f2bf(f - host_bf2f(h));
-            }
-          const size_t plane = p.arec_bytes / 2;
-          if (hipMemcpy(c->ws + p.o_arec + base * 2, hi, nrec_el * 2,
-                        hipMemcpyHostToDevice) != hipSuccess ||
-              hipMemcpy(c->ws + p.o_arec + plane + base * 2, lo, nrec_el * 2,
-                        hipMemcpyHostToDevice) != hipSuccess)
-            st[i] = SRM_E_HIP;
-        }
-      }
+  const Subject& su = p.subj[i];
+  const size_t nrec_el = (size_t)su.vp * p.KP;  // elements in its records
+  const size_t base = arec_index(p.NB, su.row0, 0);
+  std::vector<char> buf(nrec_el * 4, 0);
+  const int nt = std::max(1, std::min(n_threads(), su.v / 4096 + 1));
+  if (p.prec == SRM_FP32) {
+    float* f = reinterpret_cast<float*>(buf.data());
+    parallel_for(nt, [&](int t) {
+      for (int r = (int)((int64_t)su.v * t / nt); r < (int)((int64_t)su.v * (t + 1) / nt); ++r)
+        for (int b = 0; b < p.k; ++b)
+          f[arec_index(p.NB, su.row0 + r, b) - base] = (float)W0[(size_t)r * p.k + b];
     });
+    HIP_OR_FAIL(hipMemcpyAsync(c->ws + p.o_arec + base * 4, buf.data(), nrec_el * 4,
+                               hipMemcpyHostToDevice, c->stream));
+  } else {
+    uint16_t* hi = reinterpret_cast<uint16_t*>(buf.data());
+    uint16_t* lo = hi + nrec_el;
+    parallel_for(nt, [&](int t) {
+      for (int r = (int)((int64_t)su.v * t / nt); r < (int)((int64_t)su.v * (t + 1) / nt); ++r)
+        for (int b = 0; b < p.k; ++b) {
+          const float f = (float)W0[(size_t)r * p.k + b];
+          const uint16_t h = host_f2bf(f);
+          const size_t o = arec_index(p.NB, su.row0 + r, b) - base;
+          hi[o] = h;
+          lo[o] = host_f2bf(f - host_bf2f(h));
+        }
+    });
+    const size_t plane = p.arec_bytes / 2;
+    HIP_OR_FAIL(hipMemcpyAsync(c->ws + p.o_arec + base * 2, hi, nrec_el * 2,
+                               hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(c->ws + p.o_arec + plane + base * 2, lo, nrec_el * 2,
+                               hipMemcpyHostToDevice, c->stream));
   }
-  for (auto& x : th) x.join();
-  for (int i = 0; i < p.N; ++i)
-    if (st[i] != SRM_OK) return fail(st[i], "upload of W0[%d] failed", i);
+  // buf is released on return: the copies must have read it.
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
   return SRM_OK;
 }
 
@@ -419,30 +443,37 @@ Ptrs ptrs(const srm_ctx* c) {
 
 // E-phase + reduction + posterior: from the current A, P, rho produce the
 // E-step's S (into the "new" buffers), Sigma_s_new, tau_new and one LL.
-hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
+//  with_polar: the polar step of an iteration (P_i and rho_i^2 from G_i);
+//  init_polar: the first E-step of a drawn start (P_i = (A_i^T A_i)^-1/2 of
+//              the Gaussian in the A records; rho_i^2 stays 1);
+//  stream_pass: the E-phase partials come from a pass over Xhat (else the
+//              sample-space products have written them).
+hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass, bool init_polar) {
   const Plan& p = c->p;
   const Ptrs q = ptrs(c);
   hipStream_t st = c->stream;
   hipError_t e;
+  const Scalars* sc = c->at<Scalars>(p.o_sc);
+  const bool polar = with_polar || init_polar;
   EArgs ea{q.xh, q.xl, q.ah, q.al, c->at<Slice>(p.o_slices),
            c->at<int32_t>(p.o_rs), c->at<float>(p.o_zpart), c->at<float>(p.o_gpart),
-           p.ldt, p.npanel, with_polar ? 1 : 0};
+           p.ldt, p.npanel, polar ? 1 : 0, sc};
   if (stream_pass) {
     Phase ph(c, SRM_PHASE_EPHASE);
     if ((e = launch_ephase(st, p.KP, p.prec, p.nranges * p.npanel, ea)) != hipSuccess) return e;
   }
   // The sample-space iteration keeps each subject's partials in slice i.
-  const size_t o_tab = (p.gram && with_polar) ? p.o_subjg : p.o_subj;
-  if (with_polar) {
+  const size_t o_tab = (p.gram && !stream_pass) ? p.o_subjg : p.o_subj;
+  if (polar) {
     QArgs qa{c->at<float>(p.o_gpart), c->at<Subject>(o_tab), c->at<double>(p.o_c),
              c->at<double>(p.o_rho2), c->at<double>(p.o_p64), c->at<double>(p.o_polwork),
              c->at<double>(p.o_vprev), c->at<int32_t>(p.o_pjac), c->at<Scalars>(p.o_sc),
-             p.k, p.t};
+             p.k, p.t, init_polar ? 1 : 0};
     Phase ph(c, SRM_PHASE_POLAR);
     if ((e = launch_polar(st, p.KP, p.N, qa)) != hipSuccess) return e;
   }
   RArgs ra{c->at<float>(p.o_zpart), c->at<Subject>(o_tab), c->at<double>(p.o_p64),
-           c->at<double>(p.o_rho2), c->at<double>(p.o_ygrp), p.N, p.gsub, p.ldt};
+           c->at<double>(p.o_rho2), c->at<double>(p.o_ygrp), p.N, p.gsub, p.ldt, sc};
   {
     Phase ph(c, SRM_PHASE_EREDUCE);
     if ((e = launch_ereduce(st, p.KP, p.ncol_r, p.ngrp, ra)) != hipSuccess) return e;
@@ -450,12 +481,11 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
   PrepArgs pa{c->at<double>(p.o_rho2), c->at<double>(p.o_c), c->at<Subject>(p.o_subj),
               c->at<double>(p.o_sigcur), c->at<double>(p.o_M),
               c->at<Scalars>(p.o_sc), p.N, p.k};
-  {
-    Phase ph(c, SRM_PHASE_POSTERIOR);
-    if ((e = launch_post_prep(st, p.KP, pa)) != hipSuccess) return e;
+  Phase ph(c, SRM_PHASE_POSTERIOR);
+  if ((e = launch_post_prep(st, p.KP, pa)) != hipSuccess) return e;
   SArgs sa{c->at<double>(p.o_ygrp), c->at<double>(p.o_M), c->at<double>(p.o_s64new),
            q.shn, q.sln, c->at<double>(p.o_sspart), c->at<double>(p.o_trpart),
-           p.ngrp, p.k, p.t, p.ldt};
+           p.ngrp, p.k, p.t, p.ldt, sc};
   if ((e = launch_post_s(st, p.KP, p.prec, p.nblk_s, sa)) != hipSuccess) return e;
   double Vtot = 0.0;
   for (const auto& su : p.subj) Vtot += su.v;
@@ -463,7 +493,6 @@ hipError_t enqueue_estep(srm_ctx* c, bool with_polar, bool stream_pass) {
              c->at<double>(p.o_signew), c->at<double>(p.o_ll), c->at<Scalars>(p.o_sc),
              p.nblk_s, p.k, p.t, Vtot};
   return launch_post_fin(st, p.KP, fa);
-  }
 }
 
 // One EM iteration: M-step on the current posterior, then the next E-step.
@@ -472,6 +501,7 @@ hipError_t enqueue_iteration(srm_ctx* c) {
   const Ptrs q = ptrs(c);
   hipStream_t st = c->stream;
   hipError_t e;
+  const Scalars* sc = c->at<Scalars>(p.o_sc);
   CopyArgs ca{c->at<double>(p.o_s64new), c->at<double>(p.o_s64cur),
               c->at<uint4>(p.o_srecnew), c->at<uint4>(p.o_sreccur),
               c->at<double>(p.o_signew), c->at<double>(p.o_sigcur), c->at<Scalars>(p.o_sc),
@@ -481,38 +511,41 @@ hipError_t enqueue_iteration(srm_ctx* c) {
     const bool g64 = p.prec == SRM_FP32;
     GZArgs za{g64 ? nullptr : c->at<float>(p.o_G), g64 ? c->at<double>(p.o_G) : nullptr,
               c->at<double>(p.o_s64cur), c->at<float>(p.o_zpart),
-              c->at<double>(p.o_gz), p.t, p.ldt, p.nq, p.k};
-    GSArgs ga{c->at<double>(p.o_gz), c->at<float>(p.o_gpart), p.nq};
+              c->at<double>(p.o_gz), p.t, p.ldt, p.nq, p.k, sc};
+    GSArgs ga{c->at<double>(p.o_gz), c->at<float>(p.o_gpart), p.nq, sc};
     {
       Phase ph(c, SRM_PHASE_GRAM);
       if ((e = launch_gram_iter(st, p.KP, p.N, za, ga)) != hipSuccess) return e;
     }
     c->a_valid = false;
-    return enqueue_estep(c, true, /*stream_pass=*/false);
+    return enqueue_estep(c, true, /*stream_pass=*/false, false);
   }
   if (p.fused) {
     FusedArgs fa{q.xh, q.xl, q.shc, q.slc, c->at<Slice>(p.o_slices), c->at<int32_t>(p.o_rs),
-                 c->at<float>(p.o_zpart), c->at<float>(p.o_gpart), p.ldt};
+                 c->at<float>(p.o_zpart), c->at<float>(p.o_gpart), p.ldt, sc};
     {
       Phase ph(c, SRM_PHASE_FUSED);
       if ((e = launch_fused(st, p.KP, p.prec, p.ldt, p.nranges, fa)) != hipSuccess) return e;
     }
     c->a_valid = false;
-    return enqueue_estep(c, true, /*stream_pass=*/false);
+    return enqueue_estep(c, true, /*stream_pass=*/false, false);
   }
-  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, 0, p.total_rows, c->m_ntiles, c->m_tpw};
+  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, 0, p.total_rows, c->m_ntiles, c->m_tpw,
+           sc};
   {
     Phase ph(c, SRM_PHASE_MPHASE);
     if ((e = launch_mphase(st, p.KP, p.prec, c->m_grid, ma)) != hipSuccess) return e;
   }
   c->a_valid = true;
-  return enqueue_estep(c, true, /*stream_pass=*/true);
+  return enqueue_estep(c, true, /*stream_pass=*/true, false);
 }
 
 srm_status run_iterations(srm_ctx* c, int n) {
+  c->graph_used = false;
   for (int it = 0; it < n; ++it) {
     if (!(c->flags & SRM_NO_GRAPH) && !c->graph_ok && c->gexec == nullptr) {
-      // Capture one iteration once; fall back to direct launches on failure.
+      // Capture one iteration once; if capture or instantiation fails the
+      // iterations are launched directly (srm_get_info reports which ran).
       hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         hipError_t e2 = enqueue_iteration(c);
@@ -535,6 +568,7 @@ srm_status run_iterations(srm_ctx* c, int n) {
     }
     if (c->graph_ok) {
       HIP_OR_FAIL(hipGraphLaunch(c->gexec, c->stream));
+      c->graph_used = true;
     } else {
       HIP_OR_FAIL(enqueue_iteration(c));
     }
@@ -555,6 +589,40 @@ srm_status read_scalars(srm_ctx* c, Scalars* s) {
   return SRM_OK;
 }
 
+// Copies the carried state into the backup region (save) or back (restore).
+hipError_t copy_state_regions(srm_ctx* c, bool save) {
+  const Plan& p = c->p;
+  size_t pos = p.o_backup;
+  for (const auto& r : state_regions(p)) {
+    char* live = c->ws + r.first;
+    char* bak = c->ws + pos;
+    const hipError_t e = hipMemcpyAsync(save ? bak : live, save ? live : bak, r.second,
+                                        hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    pos += r.second;
+  }
+  return hipSuccess;
+}
+
+// After a numeric failure inside srm_fit / srm_profile: the carried state
+// goes back to what it was when the call started (the failing iteration and
+// those after it returned at once on the raised status).
+srm_status undo_failed_call(srm_ctx* c, int first_iter, srm_status err) {
+  const std::string msg = g_err;
+  if (copy_state_regions(c, false) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(SRM_E_HIP, "%s; restoring the state failed", msg.c_str());
+  c->iters = first_iter;
+  c->a_valid = false;
+  g_err = msg;
+  return err;
+}
+
+srm_status check_ready(const srm_ctx* c) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (!c->ready) return fail(SRM_E_STATE, "srm_init_end has not completed");
+  return SRM_OK;
+}
+
 }  // namespace
 
 // ---- checkpoint -----------------------------------------------------------
@@ -572,7 +640,7 @@ struct StateHeader {
 };
 
 constexpr char kStateMagic[8] = {'S', 'R', 'M', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 
 uint64_t hash_v(const Plan& p) {  // FNV-1a over the voxel counts
   uint64_t h = 1469598103934665603ull;
@@ -584,17 +652,6 @@ uint64_t hash_v(const Plan& p) {  // FNV-1a over the voxel counts
     }
   }
   return h;
-}
-
-// Workspace regions carried from one iteration to the next, in blob order.
-std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p) {
-  const size_t kk = (size_t)p.KP * p.KP * 8;
-  return {{p.o_s64cur, (size_t)p.KP * p.ldt * 8}, {p.o_s64new, (size_t)p.KP * p.ldt * 8},
-          {p.o_sreccur, p.srec_bytes},            {p.o_srecnew, p.srec_bytes},
-          {p.o_sigcur, kk},                       {p.o_signew, kk},
-          {p.o_M, kk},                            {p.o_rho2, sizeof(double) * p.N},
-          {p.o_p64, (size_t)p.N * kk},            {p.o_vprev, (size_t)p.N * kk},
-          {p.o_sc, sizeof(Scalars)},              {p.o_ll, sizeof(double) * kLLCapacity}};
 }
 
 size_t state_bytes(const Plan& p) {
@@ -622,6 +679,20 @@ StateHeader make_header(const srm_ctx* c) {
   return h;
 }
 
+// Conversion of subject i's FP32 rows [r0, r0 + n) (subject-local) from src.
+hipError_t convert_rows(srm_ctx* c, int i, const float* src, int64_t r0, int64_t n, bool last) {
+  const Plan& P = c->p;
+  const Ptrs q = ptrs(c);
+  const Subject& su = P.subj[i];
+  // The chunk that ends the subject also converts its zero padding rows.
+  const int64_t row_begin = su.row0 + r0;
+  const int64_t row_end = last ? su.row0 + su.vp : su.row0 + r0 + n;
+  ConvertArgs ca{src, r0, su.row0, su.v, P.t, P.ldt, row_begin, row_end, q.xh, q.xl,
+                 c->at<double>(P.o_mu), c->at<double>(P.o_isd), c->at<double>(P.o_rowc),
+                 c->at<Scalars>(P.o_sc), P.prec, (c->flags & SRM_ZSCORE) ? 1 : 0};
+  return launch_convert(c->stream, (int)((row_end - row_begin + 3) / 4), ca);
+}
+
 }  // namespace
 
 extern "C" {
@@ -635,34 +706,27 @@ srm_status srm_workspace_size(const srm_desc* desc, size_t* bytes) {
   return SRM_OK;
 }
 
-srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
-                    const double* const* W0, void* workspace, size_t ws_bytes) {
+srm_status srm_init_begin(srm_ctx** out, const srm_desc* desc, uint64_t seed, void* workspace,
+                          size_t ws_bytes) {
   if (!out) return fail(SRM_E_ARG, "out is NULL");
   *out = nullptr;
   Plan p;
   srm_status s = make_plan(desc, p);
   if (s != SRM_OK) return s;
-  if (!X) return fail(SRM_E_ARG, "X is NULL");
-  if (!W0) return fail(SRM_E_ARG, "W0 is NULL");
-  for (int i = 0; i < p.N; ++i) {
-    if (!X[i]) return fail(SRM_E_ARG, "X[%d] is NULL", i);
-    if (!W0[i]) return fail(SRM_E_ARG, "W0[%d] is NULL", i);
-  }
   if (!workspace) return fail(SRM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0)
     return fail(SRM_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < p.total)
     return fail(SRM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, p.total);
-  if (!(desc->flags & SRM_NO_W0_CHECK)) {
-    s = check_w0(p, W0);
-    if (s != SRM_OK) return s;
-  }
 
   srm_ctx* c = new srm_ctx();
   c->p = std::move(p);
   c->flags = desc->flags;
+  c->seed = seed;
   c->ws = static_cast<char*>(workspace);
   const Plan& P = c->p;
+  c->ingested.assign(P.N, 0);
+  c->seeded.assign(P.N, 0);
   if (desc->hip_stream) {
     c->stream = static_cast<hipStream_t>(desc->hip_stream);
   } else {
@@ -673,9 +737,21 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
     c->own_stream = true;
   }
   auto bail = [&](srm_status st) {
+    const std::string msg = g_err;
     srm_free(c);
+    g_err = msg;
     return st;
   };
+  if (c->flags & SRM_X_HOST) {
+    // Uploads run on a second stream (same default priority), so that the
+    // conversion of one staging buffer overlaps the upload of the other.
+    if (hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(SRM_E_HIP, "hipStreamCreateWithFlags failed"));
+    for (int b = 0; b < 2; ++b)
+      if (hipEventCreateWithFlags(&c->ev_up[b], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_conv[b], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(SRM_E_HIP, "hipEventCreate failed"));
+  }
 
   // M-phase grid: one residency round of equal contiguous tile ranges.
   int occ = 0;
@@ -691,13 +767,7 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
   c->m_tpw = std::max<int64_t>(1, (c->m_ntiles + want - 1) / want);
   c->m_grid = (int)((c->m_ntiles + c->m_tpw - 1) / c->m_tpw);
 
-  // Host tables.
-  std::vector<int64_t> srow0(P.N);
-  std::vector<int32_t> sv(P.N);
-  for (int i = 0; i < P.N; ++i) {
-    srow0[i] = P.subj[i].row0;
-    sv[i] = P.subj[i].v;
-  }
+  // Host tables and the starting state: rho_i^2 = 1, Sigma_s = I, P_i = I.
   Scalars sc{};
   std::vector<double> ones(P.N, 1.0);
   std::vector<double> eyeKP((size_t)P.KP * P.KP, 0.0);
@@ -706,57 +776,85 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
   for (int i = 0; i < P.N; ++i)
     for (int j = 0; j < P.k; ++j) pI[((size_t)i * P.KP + j) * P.KP + j] = 1.0;
   auto up = [&](size_t off, const void* src, size_t n) {
-    return hipMemcpy(c->ws + off, src, n, hipMemcpyHostToDevice);
+    return hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
   };
   if (up(P.o_subj, P.subj.data(), sizeof(Subject) * P.N) != hipSuccess ||
       up(P.o_slices, P.slices.data(), sizeof(Slice) * P.nslices) != hipSuccess ||
       up(P.o_rs, P.range_slice.data(), sizeof(int32_t) * (P.nranges + 1)) != hipSuccess ||
-      up(P.o_srow0, srow0.data(), sizeof(int64_t) * P.N) != hipSuccess ||
-      up(P.o_sv, sv.data(), sizeof(int32_t) * P.N) != hipSuccess ||
-      ((desc->flags & SRM_X_HOST) == 0 && up(P.o_xptr, X, sizeof(void*) * P.N) != hipSuccess) ||
       up(P.o_sc, &sc, sizeof sc) != hipSuccess ||
       up(P.o_rho2, ones.data(), sizeof(double) * P.N) != hipSuccess ||
       up(P.o_sigcur, eyeKP.data(), eyeKP.size() * 8) != hipSuccess ||
-      up(P.o_p64, pI.data(), pI.size() * 8) != hipSuccess)
+      up(P.o_p64, pI.data(), pI.size() * 8) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(SRM_E_HIP, "upload of tables failed"));
-  s = upload_w0(c, W0);
-  if (s != SRM_OK) return bail(s);
+  *out = c;
+  return SRM_OK;
+}
 
-  const Ptrs q = ptrs(c);
-  ConvertArgs ca{c->at<const float* const>(P.o_xptr), c->at<int64_t>(P.o_srow0),
-                 c->at<int32_t>(P.o_sv), P.N, P.t, P.ldt, 0, P.total_rows, nullptr, -1,
-                 q.xh, q.xl, c->at<double>(P.o_mu), c->at<double>(P.o_isd),
-                 c->at<double>(P.o_rowc), c->at<Scalars>(P.o_sc), P.prec,
-                 (desc->flags & SRM_ZSCORE) ? 1 : 0};
-  if (desc->flags & SRM_X_HOST) {
-    // Streamed ingestion: each subject's FP32 rows pass through one staging
-    // buffer in the workspace, then are demeaned and converted in place.
-    float* stage = c->at<float>(P.o_stage);
-    for (int i = 0; i < P.N; ++i) {
-      const Subject& su = P.subj[i];
-      if (hipMemcpyAsync(stage, X[i], (size_t)su.v * P.t * sizeof(float),
-                         hipMemcpyHostToDevice, c->stream) != hipSuccess)
-        return bail(fail(SRM_E_HIP, "upload of X[%d] failed", i));
-      ConvertArgs ci = ca;
-      ci.row_begin = su.row0;
-      ci.row_end = su.row0 + su.vp;
-      ci.stage = stage;
-      ci.stage_subj = i;
-      if (launch_convert(c->stream, (su.vp + 3) / 4, ci) != hipSuccess)
-        return bail(fail(SRM_E_HIP, "conversion launch failed"));
+srm_status srm_ingest(srm_ctx* c, int32_t i, const float* X_i, const double* W0_i) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (c->ready) return fail(SRM_E_STATE, "srm_init_end has already completed");
+  const Plan& P = c->p;
+  if (i < 0 || i >= P.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!X_i) return fail(SRM_E_ARG, "X[%d] is NULL", i);
+  if (c->ingested[i]) return fail(SRM_E_ARG, "subject %d was already ingested", i);
+  const Subject& su = P.subj[i];
+  if (W0_i) {
+    if (!(c->flags & SRM_NO_W0_CHECK) && !c->w0_checked) {
+      const double err = w0_error(W0_i, su.v, P.k);
+      if (!(err <= 1e-8))
+        return fail(SRM_E_ARG, "W0[%d] is not orthonormal (max|W^T W - I| = %g)", i, err);
     }
-  } else if (launch_convert(c->stream, (int)((P.total_rows + 3) / 4), ca) != hipSuccess) {
-    return bail(fail(SRM_E_HIP, "conversion launch failed"));
+    const srm_status s = upload_w0(c, i, W0_i);
+    if (s != SRM_OK) return s;
+  } else {
+    SeedArgs sa{c->ws + P.o_arec,
+                c->ws + P.o_arec + (P.prec == SRM_FP32 ? 0 : P.arec_bytes / 2), su.row0,
+                su.v, su.vp, P.k, i, c->seed, P.prec};
+    HIP_OR_FAIL(launch_seed(c->stream, P.KP, sa));
   }
+  if (c->flags & SRM_X_HOST) {
+    // Streamed ingestion: chunks of the subject's FP32 rows alternate between
+    // two staging buffers.  Uploads run on the copy stream, conversions on
+    // the compute stream; events order each buffer's reuse.
+    for (int64_t r0 = 0; r0 < su.v; r0 += P.stage_rows) {
+      const int64_t n = std::min<int64_t>(P.stage_rows, su.v - r0);
+      const int b = (int)(c->stage_seq++ & 1);
+      float* stage = c->at<float>(P.o_stage + b * P.stage_bytes);
+      HIP_OR_FAIL(hipStreamWaitEvent(c->cstream, c->ev_conv[b], 0));
+      HIP_OR_FAIL(hipMemcpyAsync(stage, X_i + r0 * P.t, (size_t)(n * P.t) * sizeof(float),
+                                 hipMemcpyHostToDevice, c->cstream));
+      HIP_OR_FAIL(hipEventRecord(c->ev_up[b], c->cstream));
+      HIP_OR_FAIL(hipStreamWaitEvent(c->stream, c->ev_up[b], 0));
+      HIP_OR_FAIL(convert_rows(c, i, stage, r0, n, r0 + n >= su.v));
+      HIP_OR_FAIL(hipEventRecord(c->ev_conv[b], c->stream));
+    }
+    // The caller may free or reuse X_i once this returns.
+    HIP_OR_FAIL(hipStreamSynchronize(c->cstream));
+  } else {
+    HIP_OR_FAIL(convert_rows(c, i, X_i, 0, su.v, true));
+    // The caller may free or reuse X_i once this returns.
+    HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  }
+  c->ingested[i] = 1;
+  c->seeded[i] = W0_i ? 0 : 1;
+  return SRM_OK;
+}
+
+srm_status srm_init_end(srm_ctx* c) {
+  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  if (c->ready) return fail(SRM_E_STATE, "srm_init_end has already completed");
+  const Plan& P = c->p;
+  for (int i = 0; i < P.N; ++i)
+    if (!c->ingested[i]) return fail(SRM_E_STATE, "subject %d has not been ingested", i);
   if (launch_rowsum(c->stream, P.N, c->at<double>(P.o_rowc), c->at<Subject>(P.o_subj),
                     c->at<double>(P.o_c)) != hipSuccess)
-    return bail(fail(SRM_E_HIP, "conversion launch failed"));
+    return fail(SRM_E_HIP, "conversion launch failed");
   Scalars chk{};
-  if (hipMemcpyAsync(&chk, c->ws + P.o_sc, sizeof chk, hipMemcpyDeviceToHost,
-                     c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    return bail(fail(SRM_E_HIP, "conversion failed"));
-  if (chk.nonfinite) return bail(fail(SRM_E_NONFINITE, "X contains NaN or Inf"));
+  HIP_OR_FAIL(hipMemcpyAsync(&chk, c->ws + P.o_sc, sizeof chk, hipMemcpyDeviceToHost,
+                             c->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  if (chk.nonfinite) return fail(SRM_E_NONFINITE, "X contains NaN or Inf");
 
   if (P.gram) {
     // Per-subject sample Gram matrices, and a subject table in which subject
@@ -766,21 +864,66 @@ srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
       sg[i].s_beg = i;
       sg[i].s_end = i + 1;
     }
-    if (up(P.o_subjg, sg.data(), sizeof(Subject) * P.N) != hipSuccess)
-      return bail(fail(SRM_E_HIP, "upload of tables failed"));
+    HIP_OR_FAIL(hipMemcpyAsync(c->ws + P.o_subjg, sg.data(), sizeof(Subject) * P.N,
+                               hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+    const Ptrs q = ptrs(c);
     const int nt = (int)(P.ldt / 64);
     const bool g64 = P.prec == SRM_FP32;
     GBArgs gb{q.xh, q.xl, c->at<Subject>(P.o_subj), g64 ? nullptr : c->at<float>(P.o_G),
               g64 ? c->at<double>(P.o_G) : nullptr, P.ldt, nt};
-    if (launch_gram_build(c->stream, P.prec, nt * (nt + 1) / 2, P.N, gb) != hipSuccess)
-      return bail(fail(SRM_E_HIP, "Gram launch failed"));
+    HIP_OR_FAIL(launch_gram_build(c->stream, P.prec, nt * (nt + 1) / 2, P.N, gb));
   }
 
-  // First E-step with W_i = W0_i (P = I), rho^2 = 1, Sigma_s = I.
-  if (enqueue_estep(c, false, true) != hipSuccess)
-    return bail(fail(SRM_E_HIP, "first E-step launch failed"));
-  s = read_scalars(c, &chk);
-  if (s != SRM_OK) return bail(s);
+  // First E-step with rho^2 = 1, Sigma_s = I and W_i = W0_i (P_i = I), or,
+  // where the library drew the start, W_i = polar factor of the drawn
+  // Gaussian (P_i = (G_i^T G_i)^-1/2, taken here for every subject).
+  bool any_seeded = false;
+  for (int i = 0; i < P.N; ++i) any_seeded |= c->seeded[i] != 0;
+  if (enqueue_estep(c, false, true, any_seeded) != hipSuccess)
+    return fail(SRM_E_HIP, "first E-step launch failed");
+  const srm_status s = read_scalars(c, &chk);
+  if (s != SRM_OK) return s;
+  c->ready = true;
+  return SRM_OK;
+}
+
+srm_status srm_init(srm_ctx** out, const srm_desc* desc, const float* const* X,
+                    const double* const* W0, uint64_t seed, void* workspace, size_t ws_bytes) {
+  if (!out) return fail(SRM_E_ARG, "out is NULL");
+  *out = nullptr;
+  Plan p;
+  srm_status s = make_plan(desc, p);
+  if (s != SRM_OK) return s;
+  if (!X) return fail(SRM_E_ARG, "X is NULL");
+  for (int i = 0; i < p.N; ++i)
+    if (!X[i]) return fail(SRM_E_ARG, "X[%d] is NULL", i);
+  if (!workspace) return fail(SRM_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(SRM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.total)
+    return fail(SRM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, p.total);
+  if (W0 && !(desc->flags & SRM_NO_W0_CHECK)) {  // all maps checked before any device call
+    std::vector<double> err(p.N, 0.0);
+    for (int i = 0; i < p.N; ++i)
+      if (W0[i]) err[i] = w0_error(W0[i], p.subj[i].v, p.k);
+    for (int i = 0; i < p.N; ++i)
+      if (!(err[i] <= 1e-8))
+        return fail(SRM_E_ARG, "W0[%d] is not orthonormal (max|W^T W - I| = %g)", i, err[i]);
+  }
+  srm_ctx* c = nullptr;
+  s = srm_init_begin(&c, desc, seed, workspace, ws_bytes);
+  if (s != SRM_OK) return s;
+  c->w0_checked = true;
+  for (int i = 0; i < p.N && s == SRM_OK; ++i)
+    s = srm_ingest(c, i, X[i], W0 ? W0[i] : nullptr);
+  if (s == SRM_OK) s = srm_init_end(c);
+  if (s != SRM_OK) {
+    const std::string msg = g_err;
+    srm_free(c);
+    g_err = msg;
+    return s;
+  }
   *out = c;
   return SRM_OK;
 }
@@ -790,15 +933,19 @@ srm_status srm_em_step(srm_ctx* c, double* loglik) {
 }
 
 srm_status srm_fit(srm_ctx* c, int32_t n_iter, double* loglik) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (n_iter < 0) return fail(SRM_E_ARG, "n_iter < 0");
+  if (n_iter == 0) return SRM_OK;
   const int first = c->iters;
-  srm_status s = run_iterations(c, n_iter);
+  HIP_OR_FAIL(copy_state_regions(c, true));
+  s = run_iterations(c, n_iter);
   if (s != SRM_OK) return s;
   Scalars sc{};
   s = read_scalars(c, &sc);
+  if (s == SRM_E_RANK || s == SRM_E_NOTPD) return undo_failed_call(c, first, s);
   if (s != SRM_OK) return s;
-  if (loglik && n_iter > 0) {
+  if (loglik) {
     // LL index j belongs to the parameters entering iteration j.
     for (int it = 0; it < n_iter; ++it) {
       const int idx = (first + it) & (kLLCapacity - 1);
@@ -818,17 +965,21 @@ static srm_status ensure_a(srm_ctx* c, int i) {
   const Subject& su = p.subj[i];
   const int64_t nt = (su.vp + 63) / 64;
   const int64_t tpw = 4;
-  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, su.row0, su.row0 + su.vp, nt, tpw};
+  MArgs ma{q.xh, q.xl, q.shc, q.slc, q.ah, q.al, p.ldt, su.row0, su.row0 + su.vp, nt, tpw,
+           c->at<Scalars>(p.o_sc)};
   HIP_OR_FAIL(launch_mphase(c->stream, p.KP, p.prec, (int)((nt + tpw - 1) / tpw), ma));
   return SRM_OK;
 }
 
 srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (n_iter < 0 || !ms) return fail(SRM_E_ARG, "invalid argument");
   for (int i = 0; i < SRM_NPHASE; ++i) ms[i] = 0.0;
   for (int i = 0; i < 2 * SRM_NPHASE; ++i)
     if (!c->ev[i]) HIP_OR_FAIL(hipEventCreate(&c->ev[i]));
+  const int first = c->iters;
+  HIP_OR_FAIL(copy_state_regions(c, true));
   c->profiling = true;
   for (int it = 0; it < n_iter; ++it) {
     for (auto& r : c->recorded) r = false;
@@ -848,7 +999,9 @@ srm_status srm_profile(srm_ctx* c, int32_t n_iter, double* ms) {
   }
   c->profiling = false;
   Scalars sc{};
-  return read_scalars(c, &sc);
+  s = read_scalars(c, &sc);
+  if (s == SRM_E_RANK || s == SRM_E_NOTPD) return undo_failed_call(c, first, s);
+  return s;
 }
 
 // S_out[:, 0:tn] = W_i^T (X[:, 0:tn] - mu_i 1^T), X with row stride ldx and
@@ -879,7 +1032,8 @@ static srm_status transform_cols(srm_ctx* c, int32_t i, const float* X, int64_t 
 
 srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_new,
                          float* S_out) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   const Plan& p = c->p;
   if (i < 0 || i >= p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
   if (!X_new || !S_out) return fail(SRM_E_ARG, "NULL buffer");
@@ -892,7 +1046,8 @@ srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_ne
 
 srm_status srm_map(srm_ctx* c, int32_t i, int32_t j, const float* X_new, int64_t t_new,
                    float* Y_out) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   const Plan& p = c->p;
   if (i < 0 || i >= p.N || j < 0 || j >= p.N) return fail(SRM_E_ARG, "subject out of range");
   if (!X_new || !Y_out) return fail(SRM_E_ARG, "NULL buffer");
@@ -921,7 +1076,8 @@ srm_status srm_map(srm_ctx* c, int32_t i, int32_t j, const float* X_new, int64_t
 }
 
 srm_status srm_get_w(srm_ctx* c, int32_t i, float* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   const Plan& p = c->p;
   if (i < 0 || i >= p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
@@ -936,25 +1092,27 @@ srm_status srm_get_w(srm_ctx* c, int32_t i, float* dst) {
 }
 
 srm_status srm_get_s(srm_ctx* c, float* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
   const Plan& p = c->p;
-  std::vector<double> s((size_t)p.KP * p.ldt);
-  HIP_OR_FAIL(hipMemcpyAsync(s.data(), c->ws + p.o_s64cur, s.size() * 8,
+  std::vector<double> sv((size_t)p.KP * p.ldt);
+  HIP_OR_FAIL(hipMemcpyAsync(sv.data(), c->ws + p.o_s64cur, sv.size() * 8,
                              hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(hipStreamSynchronize(c->stream));
   std::vector<float> f((size_t)p.k * p.t);
   for (int j = 0; j < p.k; ++j)
     for (int64_t col = 0; col < p.t; ++col)
-      f[(size_t)j * p.t + col] = (float)s[(size_t)j * p.ldt + col];
+      f[(size_t)j * p.t + col] = (float)sv[(size_t)j * p.ldt + col];
   HIP_OR_FAIL(hipMemcpyAsync(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_OR_FAIL(hipStreamSynchronize(c->stream));
   return SRM_OK;
 }
 
 srm_status srm_get_rho2(srm_ctx* c, double* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_rho2, sizeof(double) * c->p.N,
                              hipMemcpyDeviceToHost, c->stream));
@@ -963,21 +1121,23 @@ srm_status srm_get_rho2(srm_ctx* c, double* dst) {
 }
 
 srm_status srm_get_sigma_s(srm_ctx* c, double* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
   const Plan& p = c->p;
-  std::vector<double> s((size_t)p.KP * p.KP);
-  HIP_OR_FAIL(hipMemcpyAsync(s.data(), c->ws + p.o_sigcur, s.size() * 8,
+  std::vector<double> sv((size_t)p.KP * p.KP);
+  HIP_OR_FAIL(hipMemcpyAsync(sv.data(), c->ws + p.o_sigcur, sv.size() * 8,
                              hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(hipStreamSynchronize(c->stream));
   for (int a = 0; a < p.k; ++a)
-    for (int b = 0; b < p.k; ++b) dst[(size_t)a * p.k + b] = s[(size_t)a * p.KP + b];
+    for (int b = 0; b < p.k; ++b) dst[(size_t)a * p.k + b] = sv[(size_t)a * p.KP + b];
   return SRM_OK;
 }
 
 srm_status srm_get_mu(srm_ctx* c, int32_t i, double* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (i < 0 || i >= c->p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_mu + sizeof(double) * c->p.subj[i].row0,
@@ -987,7 +1147,8 @@ srm_status srm_get_mu(srm_ctx* c, int32_t i, double* dst) {
 }
 
 srm_status srm_get_scale(srm_ctx* c, int32_t i, double* dst) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (i < 0 || i >= c->p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
   if (!dst) return fail(SRM_E_ARG, "dst is NULL");
   HIP_OR_FAIL(hipMemcpyAsync(dst, c->ws + c->p.o_isd + sizeof(double) * c->p.subj[i].row0,
@@ -995,7 +1156,6 @@ srm_status srm_get_scale(srm_ctx* c, int32_t i, double* dst) {
                              c->stream));
   return SRM_OK;
 }
-
 
 srm_status srm_get_state(srm_ctx* c, void* blob, size_t* bytes) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");
@@ -1010,7 +1170,8 @@ srm_status srm_get_state(srm_ctx* c, void* blob, size_t* bytes) {
     *bytes = need;
     return fail(SRM_E_ARG, "state blob needs %zu bytes", need);
   }
-  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  const srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   const StateHeader h = make_header(c);
   char* out = static_cast<char*>(blob);
   std::memcpy(out, &h, sizeof(h));
@@ -1029,7 +1190,8 @@ srm_status srm_get_state(srm_ctx* c, void* blob, size_t* bytes) {
 }
 
 srm_status srm_set_state(srm_ctx* c, const void* blob, size_t bytes) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (!blob) return fail(SRM_E_ARG, "blob is NULL");
   const Plan& p = c->p;
   StateHeader h{};
@@ -1045,7 +1207,7 @@ srm_status srm_set_state(srm_ctx* c, const void* blob, size_t bytes) {
   if (h.bytes != mine.bytes || bytes < h.bytes)
     return fail(SRM_E_ARG, "state blob size %zu does not match %llu", bytes,
                 (unsigned long long)mine.bytes);
-  if (h.iters < 1) return fail(SRM_E_ARG, "state blob holds no iteration");
+  if (h.iters < 0) return fail(SRM_E_ARG, "state blob holds a negative iteration count");
   const char* in = static_cast<const char*>(blob);
   size_t pos = sizeof(h);
   std::vector<double> cdev(p.N);
@@ -1067,7 +1229,8 @@ srm_status srm_set_state(srm_ctx* c, const void* blob, size_t bytes) {
 }
 
 srm_status srm_get_loglik(srm_ctx* c, double* dst, int32_t capacity, int32_t* count) {
-  if (!c) return fail(SRM_E_ARG, "ctx is NULL");
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
   if (!count) return fail(SRM_E_ARG, "count is NULL");
   Scalars sc{};
   HIP_OR_FAIL(hipMemcpyAsync(&sc, c->ws + c->p.o_sc, sizeof sc, hipMemcpyDeviceToHost,
@@ -1083,6 +1246,20 @@ srm_status srm_get_loglik(srm_ctx* c, double* dst, int32_t capacity, int32_t* co
   return SRM_OK;
 }
 
+srm_status srm_get_info(const srm_ctx* c, srm_info* info) {
+  if (!c || !info) return fail(SRM_E_ARG, "NULL argument");
+  const Plan& p = c->p;
+  std::memset(info, 0, sizeof(*info));
+  info->sweep = p.gram ? SRM_SWEEP_GRAM : (p.fused ? SRM_SWEEP_ONE_PASS : SRM_SWEEP_TWO_PASS);
+  info->graph = c->graph_used ? 1 : 0;
+  info->k_padded = p.KP;
+  info->n_ranges = p.nranges;
+  info->n_slices = p.nslices;
+  info->ldt = p.ldt;
+  info->workspace_bytes = p.total;
+  return SRM_OK;
+}
+
 srm_status srm_iterations(const srm_ctx* c, int32_t* n) {
   if (!c || !n) return fail(SRM_E_ARG, "NULL argument");
   *n = c->iters;
@@ -1094,10 +1271,16 @@ const char* srm_last_error(void) { return g_err.c_str(); }
 void srm_free(srm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->cstream) (void)hipStreamSynchronize(c->cstream);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (int b = 0; b < 2; ++b) {
+    if (c->ev_up[b]) (void)hipEventDestroy(c->ev_up[b]);
+    if (c->ev_conv[b]) (void)hipEventDestroy(c->ev_conv[b]);
+  }
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cstream) (void)hipStreamDestroy(c->cstream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

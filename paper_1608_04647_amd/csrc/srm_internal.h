@@ -52,15 +52,13 @@ enum Prec { P_FP32 = 0, P_BF16 = 1, P_BF16X2 = 2 };
 
 // Kernel argument blocks (passed by value; filled by the host planner).
 struct ConvertArgs {
-  const float* const* X;     // device array of N device pointers
-  const int64_t* subj_row0;  // [N] first global row of each subject
-  const int32_t* subj_v;     // [N]
-  int32_t N;
+  const float* src;          // FP32 rows of one subject, row stride t
+  int64_t src_row0;          // subject-local index of src's first row
+  int64_t subj_row0;         // first global row of the subject
+  int32_t v;                 // the subject's voxel count
   int64_t t, ldt;
-  int64_t row_begin;         // rows [row_begin, row_end) are converted
+  int64_t row_begin;         // global rows [row_begin, row_end) are converted
   int64_t row_end;
-  const float* stage;        // if set: subject stage_subj's rows come from here
-  int32_t stage_subj;
   void* xh;
   void* xl;
   double* mu;
@@ -69,6 +67,19 @@ struct ConvertArgs {
   Scalars* sc;
   int32_t prec;
   int32_t zscore;
+};
+
+// Library-drawn random orthonormal start: subject i's A records hold a
+// Philox4x64-10 Gaussian (the polar factor is taken by the first E-step).
+struct SeedArgs {
+  void* ah;
+  void* al;
+  int64_t row0;   // first global row of the subject
+  int32_t v, vp;
+  int32_t k;
+  int32_t subj;   // subject index (Philox counter word 1)
+  uint64_t seed;  // Philox key word 0
+  int32_t prec;
 };
 
 struct MArgs {
@@ -83,6 +94,7 @@ struct MArgs {
   int64_t row_end;
   int64_t ntiles;     // ceil((row_end - row_begin) / 64)
   int64_t tiles_per_wg;
+  const Scalars* sc;  // kernels return at once when sc->status is set
 };
 
 struct EArgs {
@@ -97,6 +109,7 @@ struct EArgs {
   int64_t ldt;
   int32_t npanel;
   int32_t want_gram;
+  const Scalars* sc;
 };
 
 struct FusedArgs {
@@ -109,6 +122,7 @@ struct FusedArgs {
   float* zpart;                // [nslices][KP][ldt]
   float* gpart;                // [nslices][KP][KP]
   int64_t ldt;
+  const Scalars* sc;
 };
 
 struct RArgs {
@@ -120,6 +134,7 @@ struct RArgs {
   int32_t N;
   int32_t gsub;
   int64_t ldt;
+  const Scalars* sc;
 };
 
 struct PrepArgs {
@@ -144,6 +159,7 @@ struct SArgs {
   int32_t ngrp;
   int32_t k;
   int64_t t, ldt;
+  const Scalars* sc;
 };
 
 struct FinArgs {
@@ -184,6 +200,7 @@ struct QArgs {
   Scalars* sc;
   int32_t k;
   int64_t t;
+  int32_t init_mode;  // 1: polar factor of the drawn start only (rho^2 stays 1)
 };
 
 struct WArgs {
@@ -257,12 +274,14 @@ struct GZArgs {
   int64_t t, ldt;
   int32_t nq;
   int32_t k;
+  const Scalars* sc;
 };
 
 struct GSArgs {
   const double* gz;
   float* gpart;     // [N][KP][KP]
   int32_t nq;
+  const Scalars* sc;
 };
 
 }  // namespace srm

@@ -148,22 +148,16 @@ __device__ double block_sum_nt(double v, double* red /* >= NT / 64 */) {
 
 // ---------------------------------------------------------------------------
 // Initialisation: demean (Algorithm 1), convert, per-row ||xhat||^2.
-// One wave per (padded) global row.
+// One wave per (padded) global row of one subject.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t r = a.row_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= a.row_end) return;
-  int lo = 0, hi = a.N - 1;  // last subject with row0 <= r
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.subj_row0[mid] <= r) lo = mid; else hi = mid - 1;
-  }
-  const int64_t lr = r - a.subj_row0[lo];
-  const bool real = lr < a.subj_v[lo];
-  const float* base = (a.stage && lo == a.stage_subj) ? a.stage : a.X[lo];
-  const float* src = real ? base + lr * a.t : nullptr;
+  const int64_t lr = r - a.subj_row0;
+  const bool real = lr < a.v;
+  const float* src = real ? a.src + (lr - a.src_row0) * a.t : nullptr;
   double s = 0.0;
   bool bad = false;
   if (real) {
@@ -217,6 +211,73 @@ __global__ __launch_bounds__(256) void k_convert(ConvertArgs a) {
   if (bad) a.sc->nonfinite = 1;
 }
 
+// ---------------------------------------------------------------------------
+// Random orthonormal start drawn by the library (Algorithm 1 initialisation
+// when the caller passes no W0): the A records of subject i receive a v_i x k
+// Gaussian G, and the first E-step takes P_i = (G^T G)^-1/2, so that the
+// deferred map W_i = G P_i is the polar factor of G (Haar distributed).
+// Element e = r k + b of G is normal number e % 4 of the Philox4x64-10 block
+// with counter (e / 4, i, 0, 0) and key (seed, 0) (Salmon et al., SC 2011),
+// by the Box-Muller transform of the block's words taken as uniforms
+// u = (x / 2^11 + 1/2) 2^-53:
+//   (x0, x1) -> sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
+//   (x2, x3) -> sqrt(-2 ln u2) (cos 2 pi u3, sin 2 pi u3).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__device__ __forceinline__ double seeded_normal(uint64_t seed, int subj, uint64_t e) {
+  uint64_t c[4] = {e >> 2, (uint64_t)subj, 0, 0};
+  philox4x64_10(c, seed, 0);
+  const int j = (int)(e & 3);
+  const uint64_t xr = (j < 2) ? c[0] : c[2];
+  const uint64_t xa = (j < 2) ? c[1] : c[3];
+  const double ur = ((double)(xr >> 11) + 0.5) * 0x1p-53;
+  const double ua = ((double)(xa >> 11) + 0.5) * 0x1p-53;
+  double sn, cs;
+  sincospi(2.0 * ua, &sn, &cs);
+  return sqrt(-2.0 * log(ur)) * ((j & 1) ? sn : cs);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_seed_a(SeedArgs a) {
+  constexpr int NB = KP / 16;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.vp * KP) return;
+  const int64_t r = idx / KP;
+  const int b = (int)(idx % KP);
+  float f = 0.f;
+  if (r < a.v && b < a.k) f = (float)seeded_normal(a.seed, a.subj, (uint64_t)r * a.k + b);
+  // A-record position of (global row R, feature b)
+  const int64_t R = a.row0 + r;
+  const int64_t rb = R >> 5;
+  const int rr = (int)(R & 31);
+  const int g = (rr & 15) >> 2, e = ((rr >> 4) << 2) + (rr & 3);
+  const int lane = (b & 15) + 16 * g;
+  const int64_t o = ((rb * NB + (b >> 4)) * 64 + lane) * 8 + e;
+  if (a.prec == P_FP32) {
+    ((float*)a.ah)[o] = f;
+  } else {
+    const uint32_t h = f2bf(f);
+    ((uint16_t*)a.ah)[o] = (uint16_t)h;
+    ((uint16_t*)a.al)[o] = (uint16_t)f2bf(f - bf2f(h));
+  }
+}
+
 // c_i = ||Xhat_i||_F^2 from the per-row sums (fixed order).
 __global__ __launch_bounds__(256) void k_rowsum(const double* rowc,
                                                 const Subject* subj,
@@ -237,6 +298,7 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* rowc,
 
 template <int KP, int PREC>
 __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
+  if (a.sc->status) return;  // an earlier step of this iteration failed
   constexpr int NB = KP / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -377,6 +439,7 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
 
 template <int KP, int PREC>
 __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
+  if (a.sc->status) return;
   constexpr int NB = KP / 16;
   constexpr int NPAIR = NB * (NB + 1) / 2;
   constexpr int NG = (NPAIR + 3) / 4;
@@ -592,6 +655,7 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
 // ---------------------------------------------------------------------------
 template <int KP, int PREC, int NW>
 __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
+  if (a.sc->status) return;
   static_assert(PREC != P_FP32, "one-pass sweep is for the BF16 forms");
   static_assert(NW % 2 == 0, "chunks are whole 32-row A records");
   constexpr bool X2 = PREC == P_BF16X2;
@@ -808,6 +872,7 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
 
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void k_ereduce(RArgs a) {
+  if (a.sc->status) return;
   // Thread t holds the RJ x CW block: features RJ (t / 16) + u, TRs
   // c0 + CW (t % 16) + m.
   constexpr int RJ = KP / 16, CW = CT / 16;
@@ -990,6 +1055,7 @@ __device__ void ltl(const double* X, int k, int ld, double* out, int ldo) {
 
 template <int KP>
 __global__ __launch_bounds__(1024) void k_post_prep(PrepArgs a) {
+  if (a.sc->status) return;
   constexpr int NT = 1024;
   constexpr int LD = KP + 1;
   __shared__ double A[KP * LD];
@@ -1043,6 +1109,7 @@ __global__ __launch_bounds__(1024) void k_post_prep(PrepArgs a) {
 
 template <int KP, int PREC>
 __global__ __launch_bounds__(256) void k_post_s(SArgs a) {
+  if (a.sc->status) return;
   constexpr int CT = 16;
   constexpr int NB = KP / 16;
   __shared__ double Ys[KP][CT];
@@ -1103,6 +1170,7 @@ __global__ __launch_bounds__(256) void k_post_s(SArgs a) {
 // the column-tile partials of S S^T summed in a fixed order.
 template <int KP>
 __global__ __launch_bounds__(256) void k_post_sig(FinArgs a) {
+  if (a.sc->status) return;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= KP * KP) return;
   const int p = idx / KP, q = idx % KP;
@@ -1123,6 +1191,7 @@ __global__ __launch_bounds__(256) void k_post_sig(FinArgs a) {
 // tr(Sigma_s_new) and the log-likelihood of the parameters entering the step.
 template <int KP>
 __global__ __launch_bounds__(256) void k_post_fin(FinArgs a) {
+  if (a.sc->status) return;
   __shared__ double red[4];
   const int tid = threadIdx.x;
   double tau = 0.0;
@@ -1146,6 +1215,7 @@ __global__ __launch_bounds__(256) void k_post_fin(FinArgs a) {
 // Start of an iteration: the previous E-step's S, Sigma_s, tau become current.
 
 __global__ __launch_bounds__(256) void k_copy_state(CopyArgs a) {
+  if (a.sc->status) return;
   const int64_t stride = (int64_t)gridDim.x * 256;
   const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
   for (int64_t i = i0; i < a.n_s64; i += stride) a.s64_cur[i] = a.s64_new[i];
@@ -1207,6 +1277,7 @@ enum { POLAR_BOTH = 0, POLAR_NS = 1, POLAR_JAC = 2 };
 
 template <int KP, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
+  if (a.sc->status) return;
   constexpr int LD = KP + 1;
   // Three KP x KP buffers (G; V or the Newton-Schulz iterate X; a product
   // B) live in LDS for K padding <= 80, in global scratch above (except G
@@ -1333,7 +1404,7 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
         }
         if (tid == 0) {
           const double t = (double)a.t;
-          a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
+          if (!a.init_mode) a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
           if (MODE == POLAR_NS) a.jac[i] = 0;
         }
         return;
@@ -1516,7 +1587,7 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   if (tid == 0) {
     const double t = (double)a.t;
     const double r = (a.c[i] - 2.0 * ssq + t * a.sc->tau_cur) / (t * su.v);
-    a.rho2[i] = rank_ok ? r : 1.0;
+    if (!a.init_mode) a.rho2[i] = rank_ok ? r : 1.0;
     if (!rank_ok && a.sc->status == 0) a.sc->status = 4;  // SRM_E_RANK
   }
 }
@@ -1524,7 +1595,7 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
 // Marks the stored eigenvectors as a valid warm start (after every subject's
 // polar step of an iteration).
 __global__ void k_polar_done(Scalars* sc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc->polar_warm = 1;
+  if (threadIdx.x == 0 && blockIdx.x == 0 && sc->status == 0) sc->polar_warm = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1841,6 +1912,7 @@ __global__ __launch_bounds__(256) void k_gram_build(GBArgs a) {
 // Wave w owns TRs q0 + 16 w .. + 15 of the tile for all features.
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
+  if (a.sc->status) return;
   constexpr int NB = KP / 16;
   constexpr int PC = 64;        // TRs per staged S chunk
   constexpr int LS = PC + 4;    // padded row of the staged chunk
@@ -1925,6 +1997,7 @@ __global__ __launch_bounds__(256) void k_gram_z(GZArgs a) {
 // TRs 4 (t % 16) + m.
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_z64(GZArgs a) {
+  if (a.sc->status) return;
   constexpr int NI = KP / 16;
   constexpr int PC = 32;  // TRs per staged chunk
   constexpr int SM1 = PC * 64 + KP * (PC + 1), SM2 = 2 * KP * 65;
@@ -1994,6 +2067,7 @@ __global__ __launch_bounds__(256) void k_gram_z64(GZArgs a) {
 // gpart[i] = sum over column tiles of the Gram shares (fixed order).
 template <int KP>
 __global__ __launch_bounds__(256) void k_gram_gsum(GSArgs a) {
+  if (a.sc->status) return;
   const int i = blockIdx.x;
   for (int idx = threadIdx.x; idx < KP * KP; idx += 256) {
     double s = 0.0;
@@ -2081,6 +2155,12 @@ hipError_t launch_copy_state(hipStream_t st, const CopyArgs& a) {
   hipLaunchKernelGGL(k_copy_state, dim3(64), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+hipError_t launch_seed(hipStream_t st, int kp, const SeedArgs& a) {
+  const int64_t n = (int64_t)a.vp * kp;
+  const int grid = (int)((n + 255) / 256);
+  SRM_KP_SWITCH(kp, hipLaunchKernelGGL((k_seed_a<KP>), dim3(grid), dim3(256), 0, st, a));
+  return hipGetLastError();
+}
 hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
   // Four waves per subject (one wave per subject measured 2x slower).  Above
   // K padding 80 the Jacobi fallback runs as its own launch of 16 waves per
@@ -2091,7 +2171,9 @@ hipError_t launch_polar(hipStream_t st, int kp, int N, const QArgs& a) {
     hipLaunchKernelGGL((k_polar<KP, 256, POLAR_NS>), dim3(N), dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_polar<KP, 1024, POLAR_JAC>), dim3(N), dim3(1024), 0, st, a);
   });
-  hipLaunchKernelGGL(k_polar_done, dim3(1), dim3(64), 0, st, a.sc);
+  // The polar factor of a drawn start is no warm start for the first
+  // iteration's Gram: the stored eigenvectors stay unused.
+  if (!a.init_mode) hipLaunchKernelGGL(k_polar_done, dim3(1), dim3(64), 0, st, a.sc);
   return hipGetLastError();
 }
 hipError_t launch_get_w(hipStream_t st, int kp, const WArgs& a) {

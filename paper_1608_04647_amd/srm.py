@@ -39,18 +39,34 @@ SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE, SRM_GRAM = 
     1, 2, 4, 8, 16, 32
 
 
+SWEEPS = {0: "one_pass", 1: "two_pass", 2: "gram"}
+
+
 class SrmDesc(ctypes.Structure):
     _fields_ = [("n_subjects", ctypes.c_int32), ("v", ctypes.POINTER(ctypes.c_int64)),
                 ("t", ctypes.c_int64), ("k", ctypes.c_int32), ("prec", ctypes.c_int),
                 ("flags", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p)]
 
 
+class SrmInfo(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("k_padded", ctypes.c_int32), ("n_ranges", ctypes.c_int32),
+                ("n_slices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("ldt", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
 _P = ctypes.c_void_p
-_I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_I32, _I64, _SZ, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64
 _DP = ctypes.POINTER(ctypes.c_double)
 _sigs = {
     "srm_workspace_size": (ctypes.c_int, [ctypes.POINTER(SrmDesc), ctypes.POINTER(_SZ)]),
-    "srm_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(SrmDesc), _P, _P, _P, _SZ]),
+    "srm_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(SrmDesc), _P, _P, _U64, _P,
+                                _SZ]),
+    "srm_init_begin": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(SrmDesc), _U64, _P,
+                                      _SZ]),
+    "srm_ingest": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "srm_init_end": (ctypes.c_int, [_P]),
+    "srm_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SrmInfo)]),
     "srm_em_step": (ctypes.c_int, [_P, _DP]),
     "srm_fit": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_profile": (ctypes.c_int, [_P, _I32, _DP]),
@@ -105,76 +121,111 @@ def workspace_size(v: Sequence[int], t: int, k: int, prec: str = "fp32") -> int:
     return int(n.value)
 
 
-def random_init(v: Sequence[int], k: int, seed: int = 0) -> List[np.ndarray]:
-    """Random orthonormal starting maps (Algorithm 1 initialisation): Q of the
-    QR of a seeded Gaussian, one per subject."""
-    out = []
-    for i, vi in enumerate(v):
-        g = np.random.default_rng([seed, i]).standard_normal((int(vi), k))
-        q, r = np.linalg.qr(g)
-        out.append(q * np.where(np.diag(r) < 0, -1.0, 1.0))
-    return out
-
-
 class SRM:
     """One SRM fit on the current HIP device.
 
     X: list of N float32 arrays (v_i x t): torch CUDA tensors are used in
     place, anything else is uploaded (or, with stream_from_host, streamed
-    through the library's staging area one subject at a time).  W0: list of
-    N float64 host arrays (v_i x k, orthonormal columns); None draws random
-    orthonormal maps.  zscore standardises each voxel after demeaning; gram
-    selects the sample-space iteration on G_i = Xhat_i^T Xhat_i."""
+    through the library's staging buffers one subject at a time).  W0: list of
+    N float64 host arrays (v_i x k, orthonormal columns), or None: the library
+    then draws each subject's random orthonormal start from `seed` (entries of
+    the list may also be None).  zscore standardises each voxel after
+    demeaning; gram selects the sample-space iteration on G_i = Xhat_i^T Xhat_i.
+
+    SRM.begin(v, t, k, ...) returns a fit awaiting its subjects: ingest(i, X_i,
+    W0_i) each one (any order), then end()."""
 
     def __init__(self, X, k: int, prec: str = "fp32", W0=None, flags: int = 0,
                  seed: int = 0, stream_from_host: bool = False, zscore: bool = False,
                  gram: bool = False):
-        import torch
-        if not torch.cuda.is_available():
-            raise SRMError(SRM_E_HIP, "no HIP device visible")
-        self._torch = torch
-        dev = torch.device("cuda", torch.cuda.current_device())
-        xs = []
-        if zscore:
-            flags |= SRM_ZSCORE
-        if gram:
-            flags |= SRM_GRAM
-        if stream_from_host:
-            flags |= SRM_X_HOST
-            for x in X:
-                xs.append(np.ascontiguousarray(x, dtype=np.float32))
-        else:
-            for x in X:
-                if isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 \
-                        and x.is_contiguous():
-                    xs.append(x)
-                else:
-                    xs.append(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to(dev))
-        self.N = len(xs)
-        self.v = [int(x.shape[0]) for x in xs]
-        self.t = int(xs[0].shape[1])
-        self.k = int(k)
-        self.prec = prec
-        if W0 is None:
-            W0 = random_init(self.v, self.k, seed)
-        w0 = [np.ascontiguousarray(w, dtype=np.float64) for w in W0]
-        self._desc = make_desc(self.v, self.t, self.k, prec, flags)
-        n = _SZ()
-        _check(_lib.srm_workspace_size(ctypes.byref(self._desc), ctypes.byref(n)))
-        self.workspace_bytes = int(n.value)
-        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
-        xptr = (_P * self.N)(*[(x.ctypes.data if stream_from_host else x.data_ptr())
-                               for x in xs])
-        wptr = (_P * self.N)(*[w.ctypes.data for w in w0])
+        torch = self._setup(flags, stream_from_host, zscore, gram)
+        xs = [self._prep_x(x) for x in X]
+        self._open([int(x.shape[0]) for x in xs], int(xs[0].shape[1]), k, prec)
+        w0 = None if W0 is None else [None if w is None else
+                                      np.ascontiguousarray(w, dtype=np.float64) for w in W0]
+        xptr = (_P * self.N)(*[(x.ctypes.data if self._host else x.data_ptr()) for x in xs])
+        wptr = None if w0 is None else (_P * self.N)(*[(w.ctypes.data if w is not None else None)
+                                                       for w in w0])
         torch.cuda.synchronize()
         ctx = _P()
         t0 = time.perf_counter()
         _check(_lib.srm_init(ctypes.byref(ctx), ctypes.byref(self._desc), xptr, wptr,
-                             _P(self._ws.data_ptr()), self.workspace_bytes))
+                             int(seed), _P(self._ws.data_ptr()), self.workspace_bytes))
         # srm_init returns after its device work (it reads the device status)
         self.init_seconds = time.perf_counter() - t0
         self._ctx = ctx
-        self._dev = dev
+
+    @classmethod
+    def begin(cls, v, t: int, k: int, prec: str = "fp32", flags: int = 0, seed: int = 0,
+              stream_from_host: bool = False, zscore: bool = False, gram: bool = False):
+        """A fit awaiting its subjects (srm_init_begin)."""
+        self = cls.__new__(cls)
+        self._setup(flags, stream_from_host, zscore, gram)
+        self._open([int(x) for x in v], int(t), k, prec)
+        ctx = _P()
+        self._t0 = time.perf_counter()
+        _check(_lib.srm_init_begin(ctypes.byref(ctx), ctypes.byref(self._desc), int(seed),
+                                   _P(self._ws.data_ptr()), self.workspace_bytes))
+        self._ctx = ctx
+        return self
+
+    def ingest(self, i: int, X_i, W0_i=None):
+        """Store subject i (srm_ingest); X_i and W0_i may be released afterwards."""
+        x = self._prep_x(X_i)
+        w = None if W0_i is None else np.ascontiguousarray(W0_i, dtype=np.float64)
+        if not self._host:
+            self._torch.cuda.synchronize()  # torch's upload precedes the library's stream
+        _check(_lib.srm_ingest(self._ctx, int(i),
+                               _P(x.ctypes.data if self._host else x.data_ptr()),
+                               None if w is None else _P(w.ctypes.data)))
+
+    def end(self):
+        """srm_init_end: every subject ingested; runs the first E-step."""
+        _check(_lib.srm_init_end(self._ctx))
+        self.init_seconds = time.perf_counter() - self._t0
+        return self
+
+    def _setup(self, flags, stream_from_host, zscore, gram):
+        import torch
+        if not torch.cuda.is_available():
+            raise SRMError(SRM_E_HIP, "no HIP device visible")
+        self._torch = torch
+        self._dev = torch.device("cuda", torch.cuda.current_device())
+        self._host = bool(stream_from_host)
+        self._flags = int(flags) | (SRM_ZSCORE if zscore else 0) | (SRM_GRAM if gram else 0) \
+            | (SRM_X_HOST if stream_from_host else 0)
+        self._ctx = None
+        return torch
+
+    def _prep_x(self, x):
+        torch = self._torch
+        if self._host:
+            return np.ascontiguousarray(x, dtype=np.float32)
+        if isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 \
+                and x.is_contiguous():
+            return x
+        return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to(self._dev)
+
+    def _open(self, v, t, k, prec):
+        self.N = len(v)
+        self.v = list(v)
+        self.t = int(t)
+        self.k = int(k)
+        self.prec = prec
+        self._desc = make_desc(self.v, self.t, self.k, prec, self._flags)
+        n = _SZ()
+        _check(_lib.srm_workspace_size(ctypes.byref(self._desc), ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        self._ws = self._torch.empty(self.workspace_bytes, dtype=self._torch.uint8,
+                                     device=self._dev)
+
+    def info(self) -> dict:
+        """srm_get_info: the sweep, whether the graph ran, the plan's sizes."""
+        inf = SrmInfo()
+        _check(_lib.srm_get_info(self._ctx, ctypes.byref(inf)))
+        return {"sweep": SWEEPS.get(inf.sweep, inf.sweep), "graph": bool(inf.graph),
+                "k_padded": inf.k_padded, "n_ranges": inf.n_ranges, "n_slices": inf.n_slices,
+                "ldt": inf.ldt, "workspace_bytes": inf.workspace_bytes}
 
     # -- iteration ---------------------------------------------------------
     def fit(self, n_iter: int) -> np.ndarray:

@@ -70,7 +70,7 @@ def test_zero_subjects_and_null_pointers():
 
 def _init(d, X, W0, ws, nbytes):
     ctx = ctypes.c_void_p()
-    return srm.lib().srm_init(ctypes.byref(ctx), ctypes.byref(d), X, W0, ws, nbytes), ctx
+    return srm.lib().srm_init(ctypes.byref(ctx), ctypes.byref(d), X, W0, 0, ws, nbytes), ctx
 
 
 def test_init_argument_errors_before_any_device_call():
@@ -81,7 +81,6 @@ def test_init_argument_errors_before_any_device_call():
          for i, v in enumerate((100, 120))]
     wp = (ctypes.c_void_p * 2)(*[x.ctypes.data for x in w])
     assert _init(d, None, wp, ctypes.c_void_p(0x10000), nbytes)[0] == srm.SRM_E_ARG
-    assert _init(d, fake, None, ctypes.c_void_p(0x10000), nbytes)[0] == srm.SRM_E_ARG
     nullx = (ctypes.c_void_p * 2)(0x1000, 0)
     assert _init(d, nullx, wp, ctypes.c_void_p(0x10000), nbytes)[0] == srm.SRM_E_ARG
     assert _init(d, fake, wp, None, nbytes)[0] == srm.SRM_E_WORKSPACE
@@ -93,6 +92,29 @@ def test_init_argument_errors_before_any_device_call():
     st, _ = _init(d, fake, bp, ctypes.c_void_p(0x10000), nbytes)
     assert st == srm.SRM_E_ARG
     assert "orthonormal" in srm.lib().srm_last_error().decode()
+
+
+def test_incremental_init_argument_errors_before_any_device_call():
+    lib = srm.lib()
+    d = _desc()
+    _, nbytes = _ws(d)
+    ctx = ctypes.c_void_p()
+    assert lib.srm_init_begin(None, ctypes.byref(d), 0, ctypes.c_void_p(0x10000),
+                              nbytes) == srm.SRM_E_ARG
+    assert lib.srm_init_begin(ctypes.byref(ctx), None, 0, ctypes.c_void_p(0x10000),
+                              nbytes) == srm.SRM_E_ARG
+    assert lib.srm_init_begin(ctypes.byref(ctx), ctypes.byref(d), 0, None,
+                              nbytes) == srm.SRM_E_WORKSPACE
+    assert lib.srm_init_begin(ctypes.byref(ctx), ctypes.byref(d), 0,
+                              ctypes.c_void_p(0x10000), nbytes - 1) == srm.SRM_E_WORKSPACE
+    bad = _desc(k=0)
+    assert lib.srm_init_begin(ctypes.byref(ctx), ctypes.byref(bad), 0,
+                              ctypes.c_void_p(0x10000), nbytes) == srm.SRM_E_ARG
+    assert not ctx.value
+    assert lib.srm_ingest(None, 0, None, None) == srm.SRM_E_ARG
+    assert lib.srm_init_end(None) == srm.SRM_E_ARG
+    info = srm.SrmInfo()
+    assert lib.srm_get_info(None, ctypes.byref(info)) == srm.SRM_E_ARG
 
 
 def test_calls_on_null_context():

@@ -271,11 +271,80 @@ def test_p10_gram_form_agrees():
         assert np.abs(wa - wb).max() < 1e-10
 
 
-def test_flop_model_counts():
-    """Sec. V-A flop model: two V x T x K products, one V x K x K product and an
-    economy SVD counted as Householder QR."""
-    f = oracle.flop_model([1000], 100, 10)
-    assert f == 2 * 2 * 1000 * 100 * 10 + 2 * 1000 * 100 + 2 * 1000 * 100 - 2 / 3 * 1000
+def test_p10_streamed_gram_form_is_bitwise_the_list_form():
+    """The Gram form reads X_i and W0_i once, in order, from any iterable or
+    from per-subject summaries formed elsewhere (the form that scales to
+    workloads larger than host memory); it gives bitwise the result of the
+    list input, and w_of() rebuilds W_i of sampled subjects."""
+    w = synth.WORKLOADS["tiny"].scaled(n_subjects=5)
+    d = synth.generate(w, seed=6)
+    a = oracle.fit_gram(d["X"], w.k, 5, d["W0"], final_loglik=True)
+    b = oracle.fit_gram(iter(d["X"]), w.k, 5, iter(d["W0"]), final_loglik=True)
+    summ = [oracle.gram_summary(x, w0) for x, w0 in zip(d["X"], d["W0"])]
+    c = oracle.fit_gram_summaries(iter(summ), w.k, 5, final_loglik=True)
+    for r in (b, c):
+        for key in ("S", "Sigma_s", "rho2"):
+            assert np.array_equal(a[key], r[key]), key
+        assert a["ll"] == r["ll"] and a["ll_final"] == r["ll_final"]
+    for i in (1, 4):
+        assert np.array_equal(a["W"][i], oracle.w_of(c, i, d["X"][i]))
+    assert "W" not in b
+
+
+def test_philox_is_the_published_generator():
+    """Philox4x64-10 written from its definition equals NumPy's implementation
+    of the same generator (numpy.random.Philox, which advances its 256-bit
+    counter by one before each block), for several keys and counters."""
+    for key, start in (((5, 7), 0), ((0, 0), 41), ((2**64 - 1, 12345), 2**40)):
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                              counter=np.array([start, 0, 0, 0], dtype=np.uint64))
+        ref = bg.random_raw(4 * 6).reshape(6, 4)
+        ctr = np.arange(start + 1, start + 7, dtype=np.uint64)
+        z = np.zeros(6, dtype=np.uint64)
+        out = oracle.philox4x64([ctr, z, z, z], key)
+        assert np.array_equal(np.stack(out, axis=1), ref), key
+    # counter word 1 (the subject index of the seeded start) changes the stream
+    a = oracle.philox4x64([np.uint64(3), np.uint64(0), np.uint64(0), np.uint64(0)], (1, 0))
+    b = oracle.philox4x64([np.uint64(3), np.uint64(1), np.uint64(0), np.uint64(0)], (1, 0))
+    assert not np.array_equal(np.array(a), np.array(b))
+
+
+def test_seeded_gaussian_is_standard_normal():
+    """Box-Muller on Philox output: N(0, 1) marginals (Kolmogorov-Smirnov),
+    unit variance, no correlation between the pair members, deterministic in
+    the seed, different across subjects and seeds."""
+    from scipy import stats
+    z = oracle.seeded_gaussian(20000, 10, 3, 0)
+    assert stats.kstest(z.reshape(-1), "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 5e-3 and abs(z.var() - 1.0) < 5e-3
+    flat = z.reshape(-1)
+    assert abs(np.corrcoef(flat[0::2], flat[1::2])[0, 1]) < 5e-3
+    assert np.array_equal(z, oracle.seeded_gaussian(20000, 10, 3, 0))
+    assert not np.array_equal(z[:5], oracle.seeded_gaussian(20000, 10, 3, 1)[:5])
+    assert not np.array_equal(z[:5], oracle.seeded_gaussian(20000, 10, 4, 0)[:5])
+    # element e of a v x k draw is element e of any other shape's draw
+    assert np.array_equal(oracle.seeded_gaussian(7, 3, 3, 0).reshape(-1),
+                          z.reshape(-1)[:21])
+
+
+def test_seeded_start_is_a_haar_orthonormal_map():
+    """The library's start (no W0 given): orthonormal columns; equal to the
+    polar factor G (G^T G)^-1/2 written with eigh; and Haar on average:
+    E[W W^T] = (k / v) I for a rotation-invariant distribution."""
+    v, k = 40, 6
+    W = oracle.seeded_start(v, k, 11, 2)
+    assert np.abs(W.T @ W - np.eye(k)).max() < 1e-13
+    G = oracle.seeded_gaussian(v, k, 11, 2)
+    lam, U = np.linalg.eigh(G.T @ G)
+    assert np.abs(W - G @ (U / np.sqrt(lam)) @ U.T).max() < 1e-12
+    acc = np.zeros((v, v))
+    n = 400
+    for i in range(n):
+        Wi = oracle.seeded_start(v, k, 11, i)
+        acc += Wi @ Wi.T
+    acc /= n
+    assert np.abs(np.diag(acc) - k / v).max() < 0.06
+    assert np.abs(acc - np.diag(np.diag(acc))).max() < 0.06
 
 
 def test_p12_zscore_matches_scipy_and_standardises():

@@ -39,6 +39,18 @@ MUTATIONS = {
     "z-score: sample std (1/(t-1))": ("sd = np.sqrt(np.mean(D * D, axis=1))",
                                       "sd = np.sqrt(np.sum(D * D, axis=1) / (X.shape[1] - 1))"),
     "z-score: constant voxels not kept at zero": ("keep = sd > 0", "keep = sd >= 0"),
+    "Philox: key not advanced between rounds": ("k0 = k0 + _PHILOX_W[0]", "k0 = k0"),
+    "Philox: words of the round swapped": ("c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]",
+                                           "c = [hi0 ^ c[1] ^ k0, lo1, hi1 ^ c[3] ^ k1, lo0]"),
+    "Box-Muller: one uniform for radius and angle": (
+        "r0 * np.cos(2.0 * np.pi * u[1]), r0 * np.sin(2.0 * np.pi * u[1])",
+        "r0 * np.cos(2.0 * np.pi * u[0]), r0 * np.sin(2.0 * np.pi * u[0])"),
+    "Box-Muller: radius without the factor 2": ("r0 = np.sqrt(-2.0 * np.log(u[0]))",
+                                                "r0 = np.sqrt(-np.log(u[0]))"),
+    "Gram form: W0 start not applied": ("np.asarray(W0i, dtype=np.float64).T @ xh",
+                                        "xh[:W0i.shape[1]]"),
+    "Gram form: rho^-2 weight dropped": ("            Y += (1.0 / rho2[i]) * Z[i]\n        S, M",
+                                         "            Y += Z[i]\n        S, M"),
 }
 
 
