@@ -126,25 +126,38 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
     return g, res
 
 
-def sampled_check(g, w, seed, subjects):
-    """Final M-step of sampled subjects recomputed by the oracle from the
-    device's S and tr(Sigma_s): projector and rho^2 errors."""
-    import oracle
-    from paper_1608_04647_amd import synth
+def snapshot(g, picks):
+    """Host copies of a device fit's results for the oracle comparison."""
+    return {"S": g.S().cpu().numpy().astype(np.float64), "Sigma_s": g.sigma_s(),
+            "rho2": g.rho2(), "ll": g.loglik(), "iters": g.iterations(),
+            "W": {i: g.W(i).cpu().numpy() for i in picks}}
+
+
+def oracle_check(w, seed, snap):
+    """Errors of the device fit against the FP64 oracle run for the same
+    number of iterations on every subject (its Gram form, each subject
+    regenerated from the seed and summarised one at a time): S after the
+    Procrustes rotation, Sigma_s, every rho_i^2, every log-likelihood, and the
+    projectors of the sampled subjects."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from _parity import proj_err
-    gl = synth.draw_globals(w, seed)
-    S = g.S().cpu().numpy().astype(np.float64)
-    tau = float(np.trace(g.sigma_s()))
-    rho = g.rho2()
-    ew, er = 0.0, 0.0
-    for i in subjects:
-        X = synth.subject(w, gl, i, seed)
-        _, xh, c = oracle.demean(X)
-        Wo, r = oracle.m_step_subject(xh, c, S, tau)
-        ew = max(ew, proj_err(Wo, g.W(i).cpu().numpy()))
-        er = max(er, abs(rho[i] / r - 1))
-    return {"subjects": list(subjects), "projector": ew, "rho2": er}
+    from _parity import procrustes, proj_err
+    from _streamed import oracle_fit, oracle_w
+    n = snap["iters"]
+    t0 = time.perf_counter()
+    ora = oracle_fit(w, n, seed)
+    Q, eS, _ = procrustes(ora["S"], snap["S"])
+    eSig = float(np.linalg.norm(ora["Sigma_s"] - Q @ snap["Sigma_s"] @ Q.T)
+                 / np.linalg.norm(ora["Sigma_s"]))
+    ll_o = np.array(ora["ll"] + [ora["ll_final"]])
+    ll_g = snap["ll"][:len(ll_o)]
+    eW = max(proj_err(oracle_w(ora, w, i, seed), Wg) for i, Wg in snap["W"].items())
+    return {"oracle": f"FP64 Gram form on streamed input, all {w.n_subjects} subjects, "
+                      f"{n} iterations from the same W0",
+            "S": float(eS), "Sigma_s": eSig,
+            "rho2_max": float(np.max(np.abs(snap["rho2"] / ora["rho2"] - 1))),
+            "loglik_max": float(np.max(np.abs(ll_g - ll_o) / np.abs(ll_o))),
+            "projector_max": float(eW), "projector_subjects": sorted(snap["W"]),
+            "oracle_s": time.perf_counter() - t0}
 
 
 def cpu_baseline(w, seed, n_sub):
@@ -214,14 +227,12 @@ def main():
         f"({float(np.sum(v)) * w.t * 4 / 1e9:.1f} GB FP32)")
 
     results = {}
-    check = None
+    snap = None
     for prec in forms:
         g, res = run_form(srm, X, W0, w, v, prec, args.steps, args.warmup, args.profile_steps)
         if prec == forms[0] and not args.no_check:
-            rng = np.random.default_rng(args.seed)
-            subs = sorted(rng.choice(w.n_subjects, size=min(2, w.n_subjects), replace=False))
-            check = sampled_check(g, w, args.seed, [int(s) for s in subs])
-            log(f"[bench] sampled oracle check {check}")
+            picks = sorted({int(round(x)) for x in np.linspace(0, w.n_subjects - 1, 8)})
+            snap = snapshot(g, picks)
         results[prec] = res
         g.close()
         del g
@@ -233,7 +244,7 @@ def main():
         g.close()
         del g
         torch.cuda.empty_cache()
-    del X
+    del X, W0
     torch.cuda.empty_cache()
 
     head = results[forms[0]]
@@ -289,8 +300,10 @@ def main():
                 "streamed": head["init_s"] + n_fit * head["ms_per_step"] / 1e3},
             "k_gram_z_TFLOPs": ga["flops"] / (gms / 1e3) / 1e12 if gms > 0 else None,
             "k_gram_z_GBps": ga["bytes"] / (gms / 1e3) / 1e9 if gms > 0 else None}
-    if check is not None:
-        out["error_vs_oracle"] = check
+    if snap is not None:
+        log(f"[bench] oracle check: {snap['iters']} iterations on all {w.n_subjects} subjects")
+        out["error_vs_oracle"] = oracle_check(w, args.seed, snap)
+        log(f"[bench] oracle check {out['error_vs_oracle']}")
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 1e9) // 4 * 4
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -1277,7 +1277,12 @@ enum { POLAR_BOTH = 0, POLAR_NS = 1, POLAR_JAC = 2 };
 
 template <int KP, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
-  if (a.sc->status) return;
+  // Workgroups of this launch raise the status themselves, so it is read
+  // once per workgroup: every wave then takes the same early return.
+  __shared__ int status_;
+  if (threadIdx.x == 0) status_ = a.sc->status;
+  __syncthreads();
+  if (status_) return;
   constexpr int LD = KP + 1;
   // Three KP x KP buffers (G; V or the Newton-Schulz iterate X; a product
   // B) live in LDS for K padding <= 80, in global scratch above (except G

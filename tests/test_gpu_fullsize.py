@@ -1,12 +1,15 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py times.
 
-The 16-subject workload (16 x ~50k voxels x 1000 TRs, k = 50) is small enough
-for the complete FP64 oracle over a few iterations.  For the 1024-subject
-batched workload (51 M voxels x 500 TRs) the oracle recomputes, one subject
-at a time, the final M-step of sampled subjects from the device's S and
-tr(Sigma_s) (Eq. 4 and the rho update), and the test checks properties that
-hold at any size: orthonormal maps, a non-decreasing log-likelihood, and a
-symmetric positive definite Sigma_s.
+The 16-subject workload (16 x ~50k voxels x 1000 TRs, k = 50) runs its 20
+iterations against the complete FP64 oracle.  The 1024-subject batched
+workload (51 M voxels x 500 TRs) runs its 20 iterations against the oracle's
+t x t Gram form on streamed input: each subject is regenerated from the seed
+and reduced to G_i = Xhat_i^T Xhat_i, c_i and W0_i^T Xhat_i, so every result
+of the fit (S, Sigma_s, every rho_i^2, every log-likelihood) is compared.
+The larger workloads recompute, one subject at a time, the final M-step of
+sampled subjects from the device's S and tr(Sigma_s) (Eq. 4 and the rho
+update), and check properties that hold at any size: orthonormal maps, a
+non-decreasing log-likelihood.
 """
 import sys
 
@@ -40,7 +43,7 @@ def _say(*a):
 def test_plain16_full_size_against_complete_oracle(prec, bar, gram):
     srm = _srm()
     w = synth.WORKLOADS["plain16"]
-    n_iter = 3
+    n_iter = w.n_iter
     d = synth.generate(w, seed=0)
     _say(f"[case] plain16 full size prec={prec} gram={gram} iters={n_iter}")
     g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"], gram=gram)
@@ -53,41 +56,63 @@ def test_plain16_full_size_against_complete_oracle(prec, bar, gram):
     g.close()
 
 
-@pytest.mark.timeout(900)
-@pytest.mark.parametrize("gram", [False, True])
-def test_batch1024_full_size_sampled_m_step_and_properties(gram):
+def _say_progress(tag, n_total):
+    def f(done):
+        if done % 128 == 0 or done == n_total:
+            _say(f"[oracle] {tag}: {done}/{n_total} subjects summarised")
+    return f
+
+
+@pytest.mark.timeout(1500)
+def test_batch1024_full_trajectory_against_oracle():
+    """The 1024-subject batched workload (51 M voxels x 500 TRs, k = 50, BF16
+    hi+lo) for its 20 iterations, through the one-pass sweep and through the
+    sample-space iteration, against the FP64 oracle's Gram form on streamed
+    input (every subject regenerated and summarised one at a time): S after
+    Procrustes, Sigma_s, all 1024 rho_i^2, the log-likelihood of every
+    iteration, and projectors of 8 subjects across the range, each within
+    1e-3 (Sec. II-D, Eq. 10-11; Algorithm 1)."""
     import torch
     srm = _srm()
+    from _parity import procrustes
+    from _streamed import oracle_fit, oracle_w
     w = synth.WORKLOADS["batch1024"]
-    n_iter = 5
-    _say(f"[case] batch1024 full size gram={gram}: generating 1024 subjects on the device")
+    n_iter = w.n_iter
+    picks = (0, 137, 300, 511, 640, 777, 900, 1023)
+    _say("[case] batch1024 full trajectory: generating 1024 subjects on the device")
     X, W0, gl = synth.to_device(w, seed=0)
-    g = srm.SRM(X, w.k, prec="bf16x2", W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
-    del X
+    fits = {}
+    for gram in (False, True):
+        g = srm.SRM(X, w.k, prec="bf16x2", W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
+        g.fit(n_iter)
+        fits[g.info()["sweep"]] = {
+            "S": g.S().cpu().numpy().astype(np.float64), "Sigma_s": g.sigma_s(),
+            "rho2": g.rho2(), "ll": g.loglik(),
+            "W": {i: g.W(i).cpu().numpy() for i in picks}}
+        _say(f"[case] device fit done ({g.info()['sweep']}, graph={g.info()['graph']})")
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    del X, W0
     torch.cuda.empty_cache()
-    g.fit(n_iter)
-    ll = g.loglik()
-    assert len(ll) == n_iter + 1
-    assert np.all(np.diff(ll) >= -1e-9 * np.abs(ll[:-1])), ll
-    sig = g.sigma_s()
-    assert np.allclose(sig, sig.T, atol=1e-12)
-    assert np.linalg.eigvalsh(sig).min() > 0
-    S = g.S().cpu().numpy().astype(np.float64)
-    tau = float(np.trace(sig))
-    rho = g.rho2()
-    assert np.all(rho > 0)
-    for i in (0, 511, 1023):
-        Xi = synth.subject(w, gl, i, seed=0)
-        _, xh, c = oracle.demean(Xi)
-        Wo, r = oracle.m_step_subject(xh, c, S, tau)
-        Wg = g.W(i).cpu().numpy().astype(np.float64)
-        ep = proj_err(Wo, Wg)
-        orth = float(np.abs(Wg.T @ Wg - np.eye(w.k)).max())
-        er = abs(rho[i] / r - 1)
-        _say(f"[errors] batch1024 subject {i}: projector {ep:.2e}, rho2 {er:.2e}, "
-             f"orth {orth:.2e}")
-        assert ep <= 1e-3 and er <= 1e-3 and orth <= 1e-4
-    g.close()
+    assert set(fits) == {"one_pass", "gram"}
+    ora = oracle_fit(w, n_iter, seed=0, progress=_say_progress("batch1024", w.n_subjects))
+    ll_o = np.array(ora["ll"] + [ora["ll_final"]])
+    Wo = {i: oracle_w(ora, w, i, seed=0) for i in picks}
+    for sweep, f in fits.items():
+        Q, eS, _ = procrustes(ora["S"], f["S"])
+        eSig = np.linalg.norm(ora["Sigma_s"] - Q @ f["Sigma_s"] @ Q.T) / \
+            np.linalg.norm(ora["Sigma_s"])
+        eR = float(np.max(np.abs(f["rho2"] / ora["rho2"] - 1)))
+        assert len(f["ll"]) == len(ll_o) == n_iter + 1
+        eLL = float(np.max(np.abs(f["ll"] - ll_o) / np.abs(ll_o)))
+        eW = max(proj_err(Wo[i], f["W"][i]) for i in picks)
+        _say(f"[errors] batch1024 full trajectory {sweep}: S={eS:.2e} Sigma_s={eSig:.2e} "
+             f"rho2(max of 1024)={eR:.2e} ll(max of {n_iter + 1})={eLL:.2e} "
+             f"projector(8)={eW:.2e}")
+        assert eS <= 1e-3 and eSig <= 1e-3 and eR <= 1e-3 and eW <= 1e-3
+        assert eLL <= 1e-4
+        assert np.all(np.diff(f["ll"]) >= -1e-9 * np.abs(f["ll"][:-1])), f["ll"]
 
 
 def _sampled_m_step(g, w, gl, subjects, seed=0, prec=None):
