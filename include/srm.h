@@ -32,7 +32,8 @@
  *    pointers are ordinary process memory.
  *  - The library never allocates device memory: everything it keeps lives in
  *    the caller's workspace (see srm_workspace_size), which must stay valid
- *    and untouched until srm_free().
+ *    and untouched until srm_free().  The one exception is the static 8 MiB
+ *    array of srm_transform_static, part of the library image on each device.
  *  - All device work is enqueued on desc.hip_stream (a hipStream_t; NULL means
  *    the library creates its own non-blocking stream).  Calls that return host
  *    values synchronise that stream; the others only enqueue.
@@ -229,6 +230,21 @@ srm_status srm_profile(srm_ctx *ctx, int32_t n_iter, double *ms);
  * Valid after at least one iteration (SRM_E_STATE otherwise).  Enqueues only. */
 srm_status srm_transform(srm_ctx *ctx, int32_t i, const float *X_new,
                          int64_t t_new, float *S_out);
+
+/* srm_transform for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * S_out = W_i^T (X_new - mu_i 1^T) with the same arguments, in one launch
+ * pair over all t_new columns, its partial sums held in a static device
+ * array of 8 MiB that the library keeps on each device it runs on until the
+ * process ends (no allocation of any kind in the call).  Every call on one
+ * device shares that array: calls that overlap on one device (from any
+ * context or stream) race and must be serialised by the caller.
+ * Errors as srm_transform, plus SRM_E_ARG when one row split of t_new
+ * columns exceeds the array (t_new > 2^21 / k_padded, k_padded = k rounded up
+ * to 16) and SRM_E_HIP when the array's address could not be obtained at
+ * srm_init_begin.  Enqueues only. */
+srm_status srm_transform_static(srm_ctx *ctx, int32_t i, const float *X_new,
+                                int64_t t_new, float *S_out);
 
 /* Map new samples of subject i into subject j's voxel space through the
  * shared space (Sec. II-A): Y_out = W_j W_i^T (X_new - mu_i 1^T), i.e. the

@@ -42,6 +42,9 @@ hipError_t launch_gram_iter(hipStream_t, int, int, const GZArgs&, const GSArgs&)
 bool fused_supported(int kp, int prec, int64_t ldt);
 hipError_t launch_fused(hipStream_t, int, int, int64_t, int, const FusedArgs&);
 hipError_t occupancy_ephase(int, int, int*);
+size_t static_scratch_bytes();
+hipError_t static_scratch_setup(int dev);
+void* static_scratch_ptr(int dev);
 }  // namespace srm
 
 using namespace srm;
@@ -276,6 +279,8 @@ struct srm_ctx {
   Plan p;
   uint32_t flags = 0;
   uint64_t seed = 0;
+  int device = 0;                 // current device at srm_init_begin
+  hipError_t scratch_err = hipSuccess;  // set-up of the static scratch on it
   hipStream_t stream = nullptr;   // every kernel
   hipStream_t cstream = nullptr;  // uploads of streamed host ingestion
   bool own_stream = false;
@@ -753,6 +758,11 @@ srm_status srm_init_begin(srm_ctx** out, const srm_desc* desc, uint64_t seed, vo
         return bail(fail(SRM_E_HIP, "hipEventCreate failed"));
   }
 
+  // The static scratch of srm_transform_static: its address on this device
+  // (looked up once per device; a failure only disables that entry point).
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  c->scratch_err = static_scratch_setup(c->device);
+
   // M-phase grid: one residency round of equal contiguous tile ranges.
   int occ = 0;
   if (occupancy_mphase(P.KP, P.prec, &occ) != hipSuccess || occ < 1) occ = 1;
@@ -1042,6 +1052,44 @@ srm_status srm_transform(srm_ctx* c, int32_t i, const float* X_new, int64_t t_ne
   const srm_status sa = ensure_a(c, i);
   if (sa != SRM_OK) return sa;
   return transform_cols(c, i, X_new, t_new, t_new, S_out, t_new);
+}
+
+srm_status srm_transform_static(srm_ctx* c, int32_t i, const float* X_new, int64_t t_new,
+                                float* S_out) {
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
+  const Plan& p = c->p;
+  if (i < 0 || i >= p.N) return fail(SRM_E_ARG, "subject %d out of range", i);
+  if (!X_new || !S_out) return fail(SRM_E_ARG, "NULL buffer");
+  if (t_new < 1) return fail(SRM_E_ARG, "t_new must be >= 1");
+  if (c->iters < 1) return fail(SRM_E_STATE, "no iteration has run yet");
+  void* scr = static_scratch_ptr(c->device);
+  if (c->scratch_err != hipSuccess || !scr)
+    return fail(SRM_E_HIP, "static scratch unavailable on device %d: %s", c->device,
+                hipGetErrorString(c->scratch_err));
+  // One launch pair over all t_new columns: one row split needs KP t_new
+  // floats of the static scratch; more splits are used while they fit.
+  const size_t cap = static_scratch_bytes() / sizeof(float);
+  const size_t per_split = (size_t)p.KP * (size_t)t_new;
+  if (per_split > cap)
+    return fail(SRM_E_ARG,
+                "t_new=%lld needs %zu bytes of static scratch at k padded to %d; the maximum "
+                "is %zu bytes (t_new <= %zu)", (long long)t_new, per_split * sizeof(float), p.KP,
+                static_scratch_bytes(), cap / p.KP);
+  const Subject& su = p.subj[i];
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(
+      std::min<int64_t>(64, (su.v + 2047) / 2048), (int64_t)(cap / per_split)));
+  const srm_status sa = ensure_a(c, i);
+  if (sa != SRM_OK) return sa;
+  const Ptrs q = ptrs(c);
+  float* part = static_cast<float*>(scr);
+  const int rps = (int)((su.v + nsplit - 1) / nsplit);
+  TArgs ta{q.ah, q.al, c->at<double>(p.o_mu), c->at<double>(p.o_isd), X_new, part, su.row0,
+           t_new, t_new, su.v, rps, p.prec};
+  TFArgs tf{part, c->at<double>(p.o_p64) + (size_t)i * p.KP * p.KP, S_out, t_new, t_new,
+            nsplit, p.k};
+  HIP_OR_FAIL(launch_transform(c->stream, p.KP, nsplit, ta, tf));
+  return SRM_OK;
 }
 
 srm_status srm_map(srm_ctx* c, int32_t i, int32_t j, const float* X_new, int64_t t_new,

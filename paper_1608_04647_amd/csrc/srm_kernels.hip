@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "srm_internal.h"
 
@@ -2252,6 +2253,43 @@ hipError_t occupancy_ephase(int kp, int prec, int* blocks) {
   SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase<KP, PR>, 256, 0)));
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation transform (srm_transform_static): the
+// per-row-split partials of W_i^T (X_new - mu_i) live in this file-scope
+// array instead of the context's workspace.  Each device holds its own copy;
+// host code uses only the address hipGetSymbolAddress returns for it, looked
+// up once per device at context set-up, never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) float scratch[kStaticScratchBytes / sizeof(float)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+// Looks up this device's copy of `scratch` once (the device must be current).
+hipError_t static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+// The device address of `scratch` on device dev, or null before its set-up.
+void* static_scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace srm

@@ -71,6 +71,7 @@ _sigs = {
     "srm_fit": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_profile": (ctypes.c_int, [_P, _I32, _DP]),
     "srm_transform": (ctypes.c_int, [_P, _I32, _P, _I64, _P]),
+    "srm_transform_static": (ctypes.c_int, [_P, _I32, _P, _I64, _P]),
     "srm_map": (ctypes.c_int, [_P, _I32, _I32, _P, _I64, _P]),
     "srm_get_w": (ctypes.c_int, [_P, _I32, _P]),
     "srm_get_s": (ctypes.c_int, [_P, _P]),
@@ -319,6 +320,22 @@ class SRM:
         self._sync()
         _check(_lib.srm_transform(self._ctx, int(i), _P(x.data_ptr()), int(x.shape[1]),
                                   _P(out.data_ptr())))
+        self._sync()
+        return out
+
+    def transform_static(self, i: int, X_new, out=None):
+        """srm_transform_static: as transform, its partials in the library's
+        static device scratch (no allocation in the call); out, if given, is a
+        k x t_new float32 device tensor."""
+        torch = self._torch
+        x = X_new if (isinstance(X_new, torch.Tensor) and X_new.is_cuda) else \
+            torch.as_tensor(np.ascontiguousarray(X_new, dtype=np.float32)).to(self._dev)
+        x = x.to(torch.float32).contiguous()
+        if out is None:
+            out = torch.empty((self.k, x.shape[1]), dtype=torch.float32, device=self._dev)
+        self._sync()
+        _check(_lib.srm_transform_static(self._ctx, int(i), _P(x.data_ptr()), int(x.shape[1]),
+                                         _P(out.data_ptr())))
         self._sync()
         return out
 

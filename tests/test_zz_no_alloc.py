@@ -1,0 +1,60 @@
+"""srm_transform_static, the entry point for callers that cannot allocate:
+its partials live in the library's static device array.  Called through the
+C-ABI and compared with srm_transform (same kernels, same row splits: equal
+results) and with the oracle's W_i^T (X_new - mu_i), on two calls in a row,
+the second with a smaller input; an input beyond the array is refused."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_04647_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_transform_static_matches_transform(prec):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_04647_amd import srm
+    w = synth.Workload("ragged", 5, 33, 250, 70, 7, 8)
+    d = synth.generate(w, seed=12)
+    g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"])
+    g.fit(w.n_iter)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"])
+    lib = srm.lib()
+    rng = np.random.default_rng(5)
+    bar = 1e-4 if prec == "fp32" else 1e-3
+    for i, tn in ((3, 300), (1, 77)):  # the second call is smaller
+        _say(f"[case] transform_static prec={prec} subject={i} t_new={tn}")
+        Xn = rng.standard_normal((d["X"][i].shape[0], tn)).astype(np.float32)
+        x = torch.as_tensor(Xn).cuda()
+        out = torch.full((w.k, tn), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        st = lib.srm_transform_static(g._ctx, i, ctypes.c_void_p(x.data_ptr()), tn,
+                                      ctypes.c_void_p(out.data_ptr()))
+        assert st == srm.SRM_OK, lib.srm_last_error().decode()
+        torch.cuda.synchronize()
+        ref_dev = g.transform(i, Xn).cpu().numpy()
+        got = out.cpu().numpy()
+        assert np.array_equal(got, ref_dev)
+        ref = ora["W"][i].T @ (Xn.astype(np.float64) - ora["mu"][i][:, None])
+        lhs = g.W(i).cpu().numpy().astype(np.float64) @ got.astype(np.float64)
+        err = np.linalg.norm(lhs - ora["W"][i] @ ref) / np.linalg.norm(ora["W"][i] @ ref)
+        _say(f"[errors] transform_static {prec} subject {i} t_new={tn}: {err:.2e}")
+        assert err <= bar
+    # one row split of t_new columns must fit the 8 MiB array (k padded to 16)
+    big = 2 ** 21 // 16 + 1
+    st = lib.srm_transform_static(g._ctx, 0, ctypes.c_void_p(16), big, ctypes.c_void_p(16))
+    assert st == srm.SRM_E_ARG
+    assert "static scratch" in lib.srm_last_error().decode()
+    g.close()
