@@ -91,24 +91,97 @@ def algorithmic(w, v, prec):
             "iter_flops": mph["flops"] + eph["flops"]}
 
 
-def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
+def paper_flop_model(v, t, k):
+    """Floating-point operations of one EM iteration by the count the paper
+    uses for its Gflop/s figures (Sec. V-A): per subject, two v_i x t x k
+    matrix products, one v_i x k x k product, and an economy SVD of the
+    v_i x k matrix counted as Householder QR, 2 m n^2 - 2 n^3 / 3."""
+    v = np.asarray(v, dtype=np.float64)
+    return float(np.sum(2.0 * 2.0 * v * t * k + 2.0 * v * k * k
+                        + 2.0 * v * k * k - 2.0 * k ** 3 / 3.0))
+
+
+def time_fit(g, steps):
     import torch
-    log(f"[bench] init {prec}{' sample-space' if gram else ''}")
-    g = srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
-    # the library's own initialisation (W0 upload, conversion, G_i for the
-    # sample-space variant, first E-step); the caller's workspace allocation
-    # is not part of it
-    init_s = g.init_seconds
-    log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
-    if warmup:
-        g.fit(warmup)
     torch.cuda.synchronize()
-    log(f"[bench] timing {steps} iterations ({prec})")
     t0 = time.perf_counter()
     ll = g.fit(steps)  # synchronises the library's stream at the end
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, ll
+
+
+def open_fit(srm, X, W0, w, v, prec, gram, seed):
+    """The fit of one form: from the device-resident data, or (X is None)
+    ingested one subject at a time from host memory as the subjects are
+    generated, through the library's staging buffers."""
+    from paper_1608_04647_amd import synth
+    if X is not None:
+        return srm.SRM(X, w.k, prec=prec, W0=W0, flags=srm.SRM_NO_W0_CHECK, gram=gram)
+    t0 = time.perf_counter()
+    g = srm.SRM.begin([int(x) for x in v], w.t, w.k, prec=prec, stream_from_host=True,
+                      flags=srm.SRM_NO_W0_CHECK, gram=gram)
+    ingest_s = 0.0
+    for i, Xi, W0i in synth.iter_subjects(w, seed, threads=4):
+        t1 = time.perf_counter()
+        g.ingest(i, Xi, W0i)
+        ingest_s += time.perf_counter() - t1
+        if i % 16 == 15:
+            log(f"[bench] {i + 1}/{w.n_subjects} subjects ingested")
+    g.end()
+    g.ingest_seconds = ingest_s
+    g.gen_and_ingest_seconds = time.perf_counter() - t0
+    return g
+
+
+def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune=True,
+             table=False, seed=0):
+    log(f"[bench] init {prec}{' sample-space' if gram else ''}")
+    g = open_fit(srm, X, W0, w, v, prec, gram, seed)
+    # the library's own initialisation (W0 upload, conversion, G_i for the
+    # sample-space variant, first E-step); the caller's workspace allocation
+    # is not part of it
+    # the library's own initialisation (host ingestion: its ingest calls and
+    # srm_init_end, not the generation of the data)
+    init_s = g.init_seconds if X is not None else g.ingest_seconds + g.end_seconds
+    ingest = None
+    if X is None:
+        ingest = {"host_ingest_s": g.ingest_seconds, "generate_and_ingest_s":
+                  g.gen_and_ingest_seconds, "end_s": g.end_seconds}
+    default_shape = g.tuning()
+    tuning = {"default": default_shape}
+    if table:  # every sweep shape at the default reduction, timed alike
+        rows = []
+        for t in g.tuning_candidates():
+            if t["reduce_wgs"] != default_shape["reduce_wgs"]:
+                continue
+            g.set_tuning(t)
+            g.fit(1)
+            dt_, _ = time_fit(g, 5)
+            rows.append(dict(t, ms=1e3 * dt_ / 5))
+            log(f"[bench] shape {t}: {rows[-1]['ms']:.3f} ms/iter")
+        tuning["table"] = rows
+        g.set_tuning(default_shape)
+    if tune:
+        t0 = time.perf_counter()
+        best, best_ms = g.autotune(trials=2)
+        tuning.update(chosen=best, autotune_ms_per_iter=best_ms,
+                      autotune_s=time.perf_counter() - t0)
+        log(f"[bench] autotuned {prec}: {best} ({best_ms:.3f} ms/iter in its trials)")
+    log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
+    if warmup:
+        g.fit(warmup)
+    log(f"[bench] timing {steps} iterations ({prec})")
+    dt, ll = time_fit(g, steps)
     log(f"[bench] {prec}: {steps / dt:.2f} iters/s; profiling {prof_steps} iterations")
+    if tune and tuning["chosen"] != default_shape:
+        # the default shape on the same state, for comparison
+        cur = g.tuning()
+        g.set_tuning(default_shape)
+        g.fit(1)
+        dt_d, _ = time_fit(g, steps)
+        tuning["default_ms_per_step"] = 1e3 * dt_d / steps
+        g.set_tuning(cur)
+        log(f"[bench] default shape: {steps / dt_d:.2f} iters/s")
     ph = g.profile(prof_steps)
     ph = {k: v_ / prof_steps for k, v_ in ph.items()}
     alg = algorithmic(w, v, prec)
@@ -121,6 +194,7 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False):
         alg["gram"] = {"bytes": Nn * t * t * gb, "flops": 2.0 * Nn * k * t * t + 2.0 * Nn * k * k * t}
         alg["iter_bytes"], alg["iter_flops"] = alg["gram"]["bytes"], alg["gram"]["flops"]
     res = {"iters_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "init_s": init_s,
+           "tuning": tuning, "ingest": ingest,
            "hbm_GBps": alg["iter_bytes"] / (dt / steps) / 1e9,
            "phase_ms": ph, "alg": alg, "ll_last": float(ll[-1]) if len(ll) else None}
     return g, res
@@ -203,6 +277,10 @@ def main():
                     help="development only: fewer subjects of the same shape")
     ap.add_argument("--no-gram", action="store_true",
                     help="skip the sample-space (G_i = Xhat_i^T Xhat_i) variant")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shapes")
+    ap.add_argument("--tuning-table", action="store_true",
+                    help="also time every sweep shape of the headline form")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GB: also run one plain device copy of this size "
                          "(calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -221,15 +299,26 @@ def main():
     log(f"[bench] generating {w.name}: {w.n_subjects} subjects, v {w.v_lo}-{w.v_hi}, "
         f"t={w.t}, k={w.k}")
     t0 = time.time()
-    X, W0, gl = synth.to_device(w, args.seed)
+    gl = synth.draw_globals(w, args.seed)
     v = gl.v
-    log(f"[bench] data on device in {time.time() - t0:.1f}s "
-        f"({float(np.sum(v)) * w.t * 4 / 1e9:.1f} GB FP32)")
+    fp32_bytes = float(np.sum(v)) * w.t * 4
+    ws_max = max(srm.workspace_size(v, w.t, w.k, p) for p in forms)
+    if fp32_bytes + ws_max > 0.9 * torch.cuda.get_device_properties(0).total_memory:
+        # FP32 data and the workspace do not fit together: each form ingests
+        # the subjects one at a time from host memory
+        X = W0 = None
+        log(f"[bench] {fp32_bytes / 1e9:.1f} GB FP32 + {ws_max / 1e9:.1f} GB workspace exceed "
+            f"the device: subjects are ingested from host memory one at a time")
+    else:
+        X, W0, gl = synth.to_device(w, args.seed)
+        log(f"[bench] data on device in {time.time() - t0:.1f}s ({fp32_bytes / 1e9:.1f} GB FP32)")
 
     results = {}
     snap = None
     for prec in forms:
-        g, res = run_form(srm, X, W0, w, v, prec, args.steps, args.warmup, args.profile_steps)
+        g, res = run_form(srm, X, W0, w, v, prec, args.steps, args.warmup, args.profile_steps,
+                          tune=not args.no_autotune,
+                          table=args.tuning_table and prec == forms[0], seed=args.seed)
         if prec == forms[0] and not args.no_check:
             picks = sorted({int(round(x)) for x in np.linspace(0, w.n_subjects - 1, 8)})
             snap = snapshot(g, picks)
@@ -240,7 +329,8 @@ def main():
     gram_res = None
     if not args.no_gram:
         g, gram_res = run_form(srm, X, W0, w, v, forms[0], args.steps, args.warmup,
-                               args.profile_steps, gram=True)
+                               args.profile_steps, gram=True, tune=not args.no_autotune,
+                               seed=args.seed)
         g.close()
         del g
         torch.cuda.empty_cache()
@@ -260,9 +350,11 @@ def main():
         roof = {"bound": "hbm", "achieved": alg["bytes"] / dur / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = committed_traffic(f"k_{dom}", w.name if not args.subjects else
+    shape = head["tuning"].get("chosen", head["tuning"]["default"])
+    kname = "k_staged" if dom == "fused" and shape["sweep_kernel"] == 1 else f"k_{dom}"
+    roof["traffic"] = committed_traffic(kname, w.name if not args.subjects else
                                         f"{w.name}-{args.subjects}", hp)
-    roof["kernel"] = f"k_{dom}"
+    roof["kernel"] = kname
     roof["kernel_ms"] = ph[dom]
 
     out = {"metric": METRIC, "value": head["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
@@ -276,13 +368,16 @@ def main():
            "hbm_GBps": head["hbm_GBps"],
            "hbm_frac": head["hbm_GBps"] / HBM_PEAK_GBS,
            "phase_ms": ph,
+           "tuning": head["tuning"],
+           "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (head["ms_per_step"] / 1e3) / 1e9,
            "roofline": roof}
     for prec in forms[1:]:
         r = results[prec]
         out[f"{prec}_plain" if prec == "fp32" else prec] = {
             "iters_per_s": r["iters_per_s"], "ms_per_step": r["ms_per_step"],
-            "hbm_GBps": r["hbm_GBps"], "phase_ms": r["phase_ms"],
-            "mfma_TFLOPs": r["alg"]["iter_flops"] / (r["ms_per_step"] / 1e3) / 1e12}
+            "hbm_GBps": r["hbm_GBps"], "phase_ms": r["phase_ms"], "tuning": r["tuning"],
+            "mfma_TFLOPs": r["alg"]["iter_flops"] / (r["ms_per_step"] / 1e3) / 1e12,
+            "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (r["ms_per_step"] / 1e3) / 1e9}
         out[f"speedup_vs_{prec}"] = head["iters_per_s"] / r["iters_per_s"]
     if gram_res is not None:
         ga = gram_res["alg"]["gram"]

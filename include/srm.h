@@ -91,7 +91,7 @@ enum {
                            over the t samples (1/t).  A constant voxel is only
                            demeaned.  srm_transform and srm_map apply the same
                            per-voxel scale.                                    */
-  SRM_GRAM = 32u        /* sample-space iteration (the Discussion's change of
+  SRM_GRAM = 32u,       /* sample-space iteration (the Discussion's change of
                            complexity from voxels to samples): srm_init forms
                            G_i = Xhat_i^T Xhat_i (t x t; FP32 for the BF16
                            forms, FP64 for SRM_FP32 storage: N t^2 4 or 8 bytes
@@ -101,6 +101,13 @@ enum {
                            iterate as the streamed sweep up to rounding; pays
                            off when t is well below the voxel counts.  At most
                            65535 subjects.                                    */
+  SRM_AUTOTUNE = 64u    /* srm_init_end picks the sweep's launch shapes
+                           (srm_tuning) for this problem and device: from the
+                           on-disk cache ($SRM_TUNE_CACHE, else
+                           $HOME/.cache/srm_tune.tsv; an empty SRM_TUNE_CACHE
+                           disables it), else by srm_autotune with 2 timed
+                           iterations per shape, whose result is appended to
+                           the cache.  Without it the default shapes are used. */
 };
 
 typedef struct {
@@ -320,6 +327,50 @@ typedef struct {
   size_t workspace_bytes; /* = srm_workspace_size                                */
 } srm_info;
 srm_status srm_get_info(const srm_ctx *ctx, srm_info *info);
+
+/* Launch shapes of the sweep.  Every candidate computes the same EM iterate
+ * (Algorithm 1); they differ in how the work is cut into workgroups and so
+ * in the order of the FP32 partial sums, hence in rounding (results are
+ * bitwise reproducible for a given shape).
+ *  sweep_kernel   one-pass sweep only: SRM_KERNEL_RING (Xhat streamed from
+ *                 HBM through a register ring, read again from the caches by
+ *                 the second half) or SRM_KERNEL_STAGED (each 32-row chunk
+ *                 of Xhat loaded once into LDS and both halves read it
+ *                 there; K padding 16 or 32, 48 with t in (256, 384], 64 with t in
+ *                 (128, 256] or (384, 512])
+ *  sweep_wgs      workgroups (equal row ranges) of the streaming sweep:
+ *                 256, 512, 768, 1024 (one-pass) or 256, 512, 1024 (two-pass)
+ *  chunk_rows     rows per chunk of the one-pass sweep (ring: 64, or 16 x
+ *                 the 64-TR column panels; staged: 32); 0 otherwise
+ *  reduce_wgs     workgroups of the E-step reduction: 256, 512 or 1024
+ *  mphase_rounds  two-pass sweep: residency rounds of M-phase row tiles (1, 2);
+ *                 0 otherwise
+ * srm_get_tuning: the shapes in use (valid from srm_init_begin on).
+ * srm_set_tuning: puts one of srm_tuning_candidates in place (SRM_E_ARG for
+ *                 anything else); valid between iterations.
+ * srm_tuning_candidates: all candidates for this problem (out may be NULL to
+ *                 query *count; at most capacity are written).
+ * srm_autotune:   times candidates (one warm-up and `trials` iterations each,
+ *                 direct launches, HIP events) by coordinate search (the sweep's
+ *                 shapes, then the reduction's), restores the carried state
+ *                 after every trial, puts the fastest in place, appends it to
+ *                 the cache and returns it (best, best_ms per iteration, both
+ *                 nullable).  A numeric failure in a trial returns its status
+ *                 with the state and shapes unchanged. */
+enum { SRM_KERNEL_RING = 0, SRM_KERNEL_STAGED = 1 };
+typedef struct {
+  int32_t sweep_kernel;
+  int32_t sweep_wgs;
+  int32_t chunk_rows;
+  int32_t reduce_wgs;
+  int32_t mphase_rounds;
+  int32_t reserved[3];
+} srm_tuning;
+srm_status srm_get_tuning(const srm_ctx *ctx, srm_tuning *t);
+srm_status srm_set_tuning(srm_ctx *ctx, const srm_tuning *t);
+srm_status srm_tuning_candidates(const srm_ctx *ctx, srm_tuning *out, int32_t capacity,
+                                 int32_t *count);
+srm_status srm_autotune(srm_ctx *ctx, int32_t trials, srm_tuning *best, double *best_ms);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *srm_last_error(void);

@@ -17,6 +17,8 @@
 #include <thread>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "../../include/srm.h"
 #include "srm_internal.h"
 
@@ -40,7 +42,10 @@ hipError_t launch_map(hipStream_t, int, const MapArgs&);
 hipError_t launch_gram_build(hipStream_t, int, int, int, const GBArgs&);
 hipError_t launch_gram_iter(hipStream_t, int, int, const GZArgs&, const GSArgs&);
 bool fused_supported(int kp, int prec, int64_t ldt);
-hipError_t launch_fused(hipStream_t, int, int, int64_t, int, const FusedArgs&);
+bool fused_chunk_ok(int64_t ldt, int chunk);
+hipError_t launch_fused(hipStream_t, int, int, int64_t, int, int, const FusedArgs&);
+bool staged_supported(int kp, int prec, int64_t ldt);
+hipError_t launch_staged(hipStream_t, int, int, int64_t, int, const FusedArgs&);
 hipError_t occupancy_ephase(int, int, int*);
 size_t static_scratch_bytes();
 hipError_t static_scratch_setup(int dev);
@@ -72,13 +77,16 @@ srm_status fail(srm_status s, const char* fmt, ...) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Target number of E-phase workgroups: one full residency round on 256 CUs
-// (two 4-wave workgroups per CU).  Fixed so that the workspace size does not
-// depend on a device query.
-constexpr int kEphaseWGs = 512;
-// Fused sweep: 8-wave workgroups, about one per CU; two equal rounds.
-constexpr int kFusedWGs = 512;
+// Default launch shapes (srm_tuning; the autotuner may pick others):
+//  streaming sweep workgroups: two-pass E-phase, one residency round on 256
+//  CUs (two 4-wave workgroups per CU); one-pass sweep, 8-wave workgroups, two
+//  equal rounds of about one per CU.  Workspace sizes cover every candidate,
+//  so they do not depend on a device query.
+constexpr int kSweepWGs = 512;
 constexpr int kReduceWGs = 512;
+constexpr int kSweepWGChoices[] = {256, 512, 768, 1024};
+constexpr int kTwoPassWGChoices[] = {256, 512, 1024};
+constexpr int kReduceWGChoices[] = {256, 512, 1024};
 // Streamed host ingestion: each of the two device staging buffers holds up to
 // this many bytes of one subject's FP32 rows.
 constexpr size_t kStageBytes = (size_t)64 << 20;
@@ -87,6 +95,7 @@ struct Plan {
   int N = 0, k = 0, KP = 0, NB = 0, prec = 0;
   int64_t t = 0, ldt = 0, total_rows = 0;
   int npanel = 0, nranges = 0, nslices = 0;
+  int max_nranges = 0, max_nslices = 0, max_ngrp = 0;  // over the tuning candidates
   bool fused = false;
   bool gram = false;  // sample-space iteration on G_i = Xhat_i^T Xhat_i
   int nq = 0;         // 64-TR column tiles of G_i
@@ -136,6 +145,112 @@ srm_status validate(const srm_desc* d) {
 // and snapshotted so that a failed fit can be undone).
 std::vector<std::pair<size_t, size_t>> state_regions(const Plan& p);
 
+// Equal row ranges (multiples of 32 rows) for the streaming sweep, split at
+// subject ends into slices; the subjects' slice spans follow.
+void layout_ranges(Plan& p, int sweep_wgs) {
+  const int64_t nblk32 = p.total_rows / 32;
+  p.nranges = (int)std::max<int64_t>(
+      1, std::min<int64_t>(nblk32, p.fused ? sweep_wgs : sweep_wgs / p.npanel));
+  p.range_slice.assign(p.nranges + 1, 0);
+  p.slices.clear();
+  int si = 0;
+  for (int r = 0; r < p.nranges; ++r) {
+    int64_t b0 = nblk32 * r / p.nranges, b1 = nblk32 * (r + 1) / p.nranges;
+    p.range_slice[r] = (int32_t)p.slices.size();
+    int64_t r0 = b0 * 32;
+    const int64_t r1 = b1 * 32;
+    while (r0 < r1) {
+      while (p.subj[si].row0 + p.subj[si].vp <= r0) ++si;
+      const int64_t se = std::min<int64_t>(r1, p.subj[si].row0 + p.subj[si].vp);
+      Slice sl;
+      sl.row0 = r0;
+      sl.nrows = (int32_t)(se - r0);
+      sl.subj = si;
+      p.slices.push_back(sl);
+      r0 = se;
+    }
+  }
+  p.range_slice[p.nranges] = (int32_t)p.slices.size();
+  p.nslices = (int)p.slices.size();
+  for (auto& su : p.subj) { su.s_beg = 0; su.s_end = 0; }
+  for (int s2 = p.nslices - 1; s2 >= 0; --s2) p.subj[p.slices[s2].subj].s_beg = s2;
+  for (int s2 = 0; s2 < p.nslices; ++s2) p.subj[p.slices[s2].subj].s_end = s2 + 1;
+}
+
+// E-step reduction: subject groups x column tiles, about reduce_wgs in all.
+void layout_reduce(Plan& p, int reduce_wgs) {
+  p.ngrp = std::max(1, std::min(p.N, reduce_wgs / p.ncol_r));
+  p.gsub = (p.N + p.ngrp - 1) / p.ngrp;
+  p.ngrp = (p.N + p.gsub - 1) / p.gsub;
+}
+
+srm_tuning default_tuning(const Plan& p) {
+  srm_tuning t{};
+  // The staged one-pass kernel where it applies (measured faster at the
+  // batched workload's shape), else the register-ring kernel.
+  const bool staged = p.fused && staged_supported(p.KP, p.prec, p.ldt);
+  t.sweep_kernel = staged ? SRM_KERNEL_STAGED : SRM_KERNEL_RING;
+  t.sweep_wgs = kSweepWGs;
+  t.chunk_rows = !p.fused ? 0 : staged ? 32 : (p.ldt == 512 ? 64 : (int)(16 * (p.ldt / 64)));
+  t.reduce_wgs = kReduceWGs;
+  t.mphase_rounds = (p.fused || p.gram) ? 0 : 1;
+  return t;
+}
+
+// Every launch shape that computes this problem's sweep: the cross product of
+// the sweep's own choices and the reduction's.  All compute the same EM
+// iterate; they differ in the order of FP32 partial sums (so in rounding).
+std::vector<srm_tuning> tuning_candidates(const Plan& p) {
+  std::vector<srm_tuning> sweep;
+  const srm_tuning d = default_tuning(p);
+  if (p.gram) {
+    sweep.push_back(d);
+  } else if (p.fused) {
+    for (int w : kSweepWGChoices) {
+      const int own = 16 * (int)(p.ldt / 64);  // one 16-row block per wave
+      std::vector<int> chunks{own};
+      if (own != 64) chunks.push_back(64);
+      for (int ch : chunks) {
+        if (!fused_chunk_ok(p.ldt, ch)) continue;
+        srm_tuning t = d;
+        t.sweep_kernel = SRM_KERNEL_RING;
+        t.sweep_wgs = w;
+        t.chunk_rows = ch;
+        sweep.push_back(t);
+      }
+      if (staged_supported(p.KP, p.prec, p.ldt)) {
+        srm_tuning t = d;
+        t.sweep_kernel = SRM_KERNEL_STAGED;
+        t.sweep_wgs = w;
+        t.chunk_rows = 32;
+        sweep.push_back(t);
+      }
+    }
+  } else {
+    for (int w : kTwoPassWGChoices)
+      for (int mr : {1, 2}) {
+        srm_tuning t = d;
+        t.sweep_wgs = w;
+        t.mphase_rounds = mr;
+        sweep.push_back(t);
+      }
+  }
+  std::vector<srm_tuning> all;
+  for (const auto& t : sweep)
+    for (int r : kReduceWGChoices) {
+      srm_tuning u = t;
+      u.reduce_wgs = r;
+      all.push_back(u);
+    }
+  return all;
+}
+
+bool same_tuning(const srm_tuning& a, const srm_tuning& b) {
+  return a.sweep_kernel == b.sweep_kernel && a.sweep_wgs == b.sweep_wgs &&
+         a.chunk_rows == b.chunk_rows && a.reduce_wgs == b.reduce_wgs &&
+         a.mphase_rounds == b.mphase_rounds;
+}
+
 srm_status make_plan(const srm_desc* d, Plan& p) {
   srm_status s = validate(d);
   if (s != SRM_OK) return s;
@@ -164,39 +279,19 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   // E-phase: equal row ranges (multiples of 32 rows) split at subject ends.
   p.npanel = (int)((p.ldt + 255) / 256);
   p.fused = fused_supported(p.KP, p.prec, p.ldt) && !(d->flags & (SRM_TWO_PASS | SRM_GRAM));
-  const int64_t nblk32 = p.total_rows / 32;
-  p.nranges = (int)std::max<int64_t>(
-      1, std::min<int64_t>(nblk32, p.fused ? kFusedWGs : kEphaseWGs / p.npanel));
-  p.range_slice.assign(p.nranges + 1, 0);
-  p.slices.clear();
-  int si = 0;
-  for (int r = 0; r < p.nranges; ++r) {
-    int64_t b0 = nblk32 * r / p.nranges, b1 = nblk32 * (r + 1) / p.nranges;
-    p.range_slice[r] = (int32_t)p.slices.size();
-    int64_t r0 = b0 * 32;
-    const int64_t r1 = b1 * 32;
-    while (r0 < r1) {
-      while (p.subj[si].row0 + p.subj[si].vp <= r0) ++si;
-      const int64_t se = std::min<int64_t>(r1, p.subj[si].row0 + p.subj[si].vp);
-      Slice sl;
-      sl.row0 = r0;
-      sl.nrows = (int32_t)(se - r0);
-      sl.subj = si;
-      p.slices.push_back(sl);
-      r0 = se;
-    }
-  }
-  p.range_slice[p.nranges] = (int32_t)p.slices.size();
-  p.nslices = (int)p.slices.size();
-  for (auto& su : p.subj) { su.s_beg = 0; su.s_end = 0; }
-  for (int s2 = p.nslices - 1; s2 >= 0; --s2) p.subj[p.slices[s2].subj].s_beg = s2;
-  for (int s2 = 0; s2 < p.nslices; ++s2) p.subj[p.slices[s2].subj].s_end = s2 + 1;
-  // reduction geometry
   p.rct = ereduce_ct(p.KP);
   p.ncol_r = (int)(p.ldt / p.rct);
-  p.ngrp = std::max(1, std::min(p.N, kReduceWGs / p.ncol_r));
-  p.gsub = (p.N + p.ngrp - 1) / p.ngrp;
-  p.ngrp = (p.N + p.gsub - 1) / p.gsub;
+  // Workspace for the largest range and reduction layouts of any candidate.
+  for (const auto& t : tuning_candidates(p)) {
+    layout_ranges(p, t.sweep_wgs);
+    layout_reduce(p, t.reduce_wgs);
+    p.max_nranges = std::max(p.max_nranges, p.nranges);
+    p.max_nslices = std::max(p.max_nslices, p.nslices);
+    p.max_ngrp = std::max(p.max_ngrp, p.ngrp);
+  }
+  const srm_tuning t0 = default_tuning(p);
+  layout_ranges(p, t0.sweep_wgs);
+  layout_reduce(p, t0.reduce_wgs);
   p.nblk_s = (int)(p.ldt / 16);
 
   // workspace layout
@@ -215,12 +310,12 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_c = take(sizeof(double) * p.N);
   p.arec_bytes = (size_t)p.total_rows * p.KP * 4;  // FP32, or 2 bf16 planes
   p.o_arec = take(p.arec_bytes);
-  p.zpart_bytes = (size_t)p.nslices * p.KP * p.ldt * 4;
+  p.zpart_bytes = (size_t)p.max_nslices * p.KP * p.ldt * 4;
   p.o_zpart = take(p.zpart_bytes);
-  p.o_gpart = take((size_t)p.nslices * p.KP * p.KP * 4);
+  p.o_gpart = take((size_t)p.max_nslices * p.KP * p.KP * 4);
   p.o_p64 = take((size_t)p.N * p.KP * p.KP * 8);
   p.o_rho2 = take(sizeof(double) * p.N);
-  p.o_ygrp = take((size_t)p.ngrp * p.KP * p.ldt * 8);
+  p.o_ygrp = take((size_t)p.max_ngrp * p.KP * p.ldt * 8);
   p.o_s64cur = take((size_t)p.KP * p.ldt * 8);
   p.o_s64new = take((size_t)p.KP * p.ldt * 8);
   p.srec_bytes = (size_t)p.KP * p.ldt * 4;
@@ -237,8 +332,8 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
   p.o_sc = take(sizeof(Scalars));
   p.o_ll = take(sizeof(double) * kLLCapacity);
   p.o_subj = take(sizeof(Subject) * p.N);
-  p.o_slices = take(sizeof(Slice) * p.nslices);
-  p.o_rs = take(sizeof(int32_t) * (p.nranges + 1));
+  p.o_slices = take(sizeof(Slice) * p.max_nslices);
+  p.o_rs = take(sizeof(int32_t) * (p.max_nranges + 1));
   if (p.gram) {
     p.nq = (int)(p.ldt / 64);
     if ((int64_t)p.nq * (p.nq + 1) / 2 * p.N >= ((int64_t)1 << 31))
@@ -288,14 +383,16 @@ struct srm_ctx {
   hipEvent_t ev_conv[2] = {};     // staging buffer b converted (compute stream)
   int64_t stage_seq = 0;          // staging buffers used so far
   char* ws = nullptr;
-  int m_grid = 0;
+  int m_grid = 0, m_occ = 1, m_ncu = 256;
   int64_t m_tpw = 0, m_ntiles = 0;
   int iters = 0;
   bool ready = false;             // srm_init_end completed
   bool w0_checked = false;        // srm_init checked every W0_i before ingesting
   std::vector<char> ingested;     // per subject, between init_begin and init_end
   std::vector<char> seeded;       // per subject: start drawn by the library
+  srm_tuning tune{};               // launch shapes in use
   bool graph_ok = false;
+  bool capture_failed = false;    // capture or instantiation failed once
   bool graph_used = false;        // the last srm_fit replayed the captured graph
   bool a_valid = true;            // A records in HBM match the current S (two-pass)
   hipGraph_t graph = nullptr;
@@ -530,7 +627,10 @@ hipError_t enqueue_iteration(srm_ctx* c) {
                  c->at<float>(p.o_zpart), c->at<float>(p.o_gpart), p.ldt, sc};
     {
       Phase ph(c, SRM_PHASE_FUSED);
-      if ((e = launch_fused(st, p.KP, p.prec, p.ldt, p.nranges, fa)) != hipSuccess) return e;
+      e = c->tune.sweep_kernel == SRM_KERNEL_STAGED
+              ? launch_staged(st, p.KP, p.prec, p.ldt, p.nranges, fa)
+              : launch_fused(st, p.KP, p.prec, p.ldt, p.nranges, c->tune.chunk_rows, fa);
+      if (e != hipSuccess) return e;
     }
     c->a_valid = false;
     return enqueue_estep(c, true, /*stream_pass=*/false, false);
@@ -548,7 +648,7 @@ hipError_t enqueue_iteration(srm_ctx* c) {
 srm_status run_iterations(srm_ctx* c, int n) {
   c->graph_used = false;
   for (int it = 0; it < n; ++it) {
-    if (!(c->flags & SRM_NO_GRAPH) && !c->graph_ok && c->gexec == nullptr) {
+    if (!(c->flags & SRM_NO_GRAPH) && !c->capture_failed && !c->graph_ok) {
       // Capture one iteration once; if capture or instantiation fails the
       // iterations are launched directly (srm_get_info reports which ran).
       hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
@@ -569,7 +669,7 @@ srm_status run_iterations(srm_ctx* c, int n) {
         }
       }
       (void)hipGetLastError();
-      if (!c->graph_ok) c->flags |= SRM_NO_GRAPH;
+      if (!c->graph_ok) c->capture_failed = true;
     }
     if (c->graph_ok) {
       HIP_OR_FAIL(hipGraphLaunch(c->gexec, c->stream));
@@ -622,10 +722,134 @@ srm_status undo_failed_call(srm_ctx* c, int first_iter, srm_status err) {
   return err;
 }
 
+// Puts launch shape t (one of tuning_candidates) in place: the range and
+// reduction layouts, their device tables, the M-phase grid; the captured
+// graph (whose launches carried the old shapes) is dropped.
+srm_status apply_tuning(srm_ctx* c, const srm_tuning& t) {
+  Plan& P = c->p;
+  bool ok = false;
+  for (const auto& u : tuning_candidates(P)) ok = ok || same_tuning(u, t);
+  if (!ok)
+    return fail(SRM_E_ARG, "launch shape (kernel %d, %d sweep workgroups, chunk %d, %d reduce "
+                "workgroups, %d M-phase rounds) is not a candidate for this problem",
+                t.sweep_kernel, t.sweep_wgs, t.chunk_rows, t.reduce_wgs, t.mphase_rounds);
+  layout_ranges(P, t.sweep_wgs);
+  layout_reduce(P, t.reduce_wgs);
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_OR_FAIL(up(P.o_subj, P.subj.data(), sizeof(Subject) * P.N));
+  HIP_OR_FAIL(up(P.o_slices, P.slices.data(), sizeof(Slice) * P.nslices));
+  HIP_OR_FAIL(up(P.o_rs, P.range_slice.data(), sizeof(int32_t) * (P.nranges + 1)));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));  // the host tables are rebuilt later
+  // M-phase grid: mphase_rounds residency rounds of equal contiguous tile ranges.
+  c->m_ntiles = (P.total_rows + 63) / 64;
+  const int64_t want = (int64_t)c->m_occ * c->m_ncu * std::max(1, t.mphase_rounds);
+  c->m_tpw = std::max<int64_t>(1, (c->m_ntiles + want - 1) / want);
+  c->m_grid = (int)((c->m_ntiles + c->m_tpw - 1) / c->m_tpw);
+  c->tune = t;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_ok = false;
+  return SRM_OK;
+}
+
 srm_status check_ready(const srm_ctx* c) {
   if (!c) return fail(SRM_E_ARG, "ctx is NULL");
   if (!c->ready) return fail(SRM_E_STATE, "srm_init_end has not completed");
   return SRM_OK;
+}
+
+// Milliseconds per iteration of launch shape t: one warm-up iteration and
+// `trials` timed ones (direct launches, HIP events on the context's stream),
+// after which the carried state is put back as it was.  *bad receives the
+// status an iteration raised (0: none).
+srm_status time_tuning(srm_ctx* c, const srm_tuning& t, int trials, hipEvent_t e0,
+                       hipEvent_t e1, double* ms, int* bad) {
+  srm_status st = apply_tuning(c, t);
+  if (st != SRM_OK) return st;
+  HIP_OR_FAIL(enqueue_iteration(c));
+  HIP_OR_FAIL(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < trials; ++i) HIP_OR_FAIL(enqueue_iteration(c));
+  HIP_OR_FAIL(hipEventRecord(e1, c->stream));
+  HIP_OR_FAIL(hipEventSynchronize(e1));
+  float f = 0.f;
+  HIP_OR_FAIL(hipEventElapsedTime(&f, e0, e1));
+  *ms = (double)f / trials;
+  Scalars sc{};
+  HIP_OR_FAIL(hipMemcpyAsync(&sc, c->ws + c->p.o_sc, sizeof sc, hipMemcpyDeviceToHost,
+                             c->stream));
+  HIP_OR_FAIL(copy_state_regions(c, false));
+  HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+  *bad = sc.status;
+  return SRM_OK;
+}
+
+// On-disk cache of tuned shapes: one line per problem, "key<TAB>kernel
+// sweep_wgs chunk reduce_wgs mphase_rounds<TAB>ms"; the last line of a key
+// wins.  The file is $SRM_TUNE_CACHE (empty: no cache), else
+// $HOME/.cache/srm_tune.tsv.
+std::string tune_cache_path() {
+  const char* e = std::getenv("SRM_TUNE_CACHE");
+  if (e) return std::string(e);
+  const char* h = std::getenv("HOME");
+  if (!h || !*h) return std::string();
+  return std::string(h) + "/.cache/srm_tune.tsv";
+}
+
+std::string tune_key(const srm_ctx* c) {
+  const Plan& p = c->p;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int ncu = 0;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    ncu = prop.multiProcessorCount;
+  }
+  for (auto& ch : arch)
+    if (ch == '\t' || ch == ' ' || ch == '\n') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s/%dcu prec=%d kp=%d ldt=%lld sweep=%d n=%d rows=%lld",
+           arch.c_str(), ncu, p.prec, p.KP, (long long)p.ldt,
+           p.gram ? 2 : (p.fused ? 0 : 1), p.N, (long long)p.total_rows);
+  return std::string(buf);
+}
+
+bool tune_cache_find(const srm_ctx* c, srm_tuning* t) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string key = tune_key(c);
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    const char* tab = std::strchr(line, '\t');
+    if (!tab || (size_t)(tab - line) != key.size() || std::strncmp(line, key.c_str(), key.size()))
+      continue;
+    srm_tuning u{};
+    if (std::sscanf(tab + 1, "%d %d %d %d %d", &u.sweep_kernel, &u.sweep_wgs, &u.chunk_rows,
+                    &u.reduce_wgs, &u.mphase_rounds) == 5) {
+      *t = u;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const srm_ctx* c, const srm_tuning& t, double ms) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%d %d %d %d %d\t%.4f\n", tune_key(c).c_str(), t.sweep_kernel,
+               t.sweep_wgs, t.chunk_rows, t.reduce_wgs, t.mphase_rounds, ms);
+  std::fclose(f);
 }
 
 }  // namespace
@@ -763,7 +987,7 @@ srm_status srm_init_begin(srm_ctx** out, const srm_desc* desc, uint64_t seed, vo
   if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   c->scratch_err = static_scratch_setup(c->device);
 
-  // M-phase grid: one residency round of equal contiguous tile ranges.
+  // M-phase occupancy, for its grid (apply_tuning).
   int occ = 0;
   if (occupancy_mphase(P.KP, P.prec, &occ) != hipSuccess || occ < 1) occ = 1;
   int dev = 0, ncu = 256;
@@ -772,10 +996,12 @@ srm_status srm_init_begin(srm_ctx** out, const srm_desc* desc, uint64_t seed, vo
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
       ncu = prop.multiProcessorCount;
   }
-  c->m_ntiles = (P.total_rows + 63) / 64;
-  const int64_t want = (int64_t)occ * ncu;
-  c->m_tpw = std::max<int64_t>(1, (c->m_ntiles + want - 1) / want);
-  c->m_grid = (int)((c->m_ntiles + c->m_tpw - 1) / c->m_tpw);
+  c->m_occ = occ;
+  c->m_ncu = ncu;
+  {
+    const srm_status st = apply_tuning(c, default_tuning(P));
+    if (st != SRM_OK) return bail(st);
+  }
 
   // Host tables and the starting state: rho_i^2 = 1, Sigma_s = I, P_i = I.
   Scalars sc{};
@@ -788,10 +1014,7 @@ srm_status srm_init_begin(srm_ctx** out, const srm_desc* desc, uint64_t seed, vo
   auto up = [&](size_t off, const void* src, size_t n) {
     return hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
   };
-  if (up(P.o_subj, P.subj.data(), sizeof(Subject) * P.N) != hipSuccess ||
-      up(P.o_slices, P.slices.data(), sizeof(Slice) * P.nslices) != hipSuccess ||
-      up(P.o_rs, P.range_slice.data(), sizeof(int32_t) * (P.nranges + 1)) != hipSuccess ||
-      up(P.o_sc, &sc, sizeof sc) != hipSuccess ||
+  if (up(P.o_sc, &sc, sizeof sc) != hipSuccess ||
       up(P.o_rho2, ones.data(), sizeof(double) * P.N) != hipSuccess ||
       up(P.o_sigcur, eyeKP.data(), eyeKP.size() * 8) != hipSuccess ||
       up(P.o_p64, pI.data(), pI.size() * 8) != hipSuccess ||
@@ -895,6 +1118,17 @@ srm_status srm_init_end(srm_ctx* c) {
   const srm_status s = read_scalars(c, &chk);
   if (s != SRM_OK) return s;
   c->ready = true;
+  if (c->flags & SRM_AUTOTUNE) {
+    // Launch shapes: from the on-disk cache for this problem and device, else
+    // by timed trials (which leave the state as the first E-step left it).
+    srm_tuning t{};
+    if (tune_cache_find(c, &t) && apply_tuning(c, t) == SRM_OK) return SRM_OK;
+    const srm_status st = srm_autotune(c, 2, nullptr, nullptr);
+    if (st != SRM_OK) {
+      c->ready = false;
+      return st;
+    }
+  }
   return SRM_OK;
 }
 
@@ -1291,6 +1525,91 @@ srm_status srm_get_loglik(srm_ctx* c, double* dst, int32_t capacity, int32_t* co
       HIP_OR_FAIL(hipMemcpy(dst + j, c->ws + c->p.o_ll + sizeof(double) * j, sizeof(double),
                             hipMemcpyDeviceToHost));
   }
+  return SRM_OK;
+}
+
+srm_status srm_get_tuning(const srm_ctx* c, srm_tuning* t) {
+  if (!c || !t) return fail(SRM_E_ARG, "NULL argument");
+  *t = c->tune;
+  return SRM_OK;
+}
+
+srm_status srm_set_tuning(srm_ctx* c, const srm_tuning* t) {
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
+  if (!t) return fail(SRM_E_ARG, "tuning is NULL");
+  return apply_tuning(c, *t);
+}
+
+srm_status srm_tuning_candidates(const srm_ctx* c, srm_tuning* out, int32_t capacity,
+                                 int32_t* count) {
+  if (!c || !count) return fail(SRM_E_ARG, "NULL argument");
+  const auto all = tuning_candidates(c->p);
+  *count = (int32_t)all.size();
+  if (out)
+    for (int i = 0; i < std::min<int>(capacity, (int)all.size()); ++i) out[i] = all[i];
+  return SRM_OK;
+}
+
+srm_status srm_autotune(srm_ctx* c, int32_t trials, srm_tuning* best, double* best_ms) {
+  srm_status s = check_ready(c);
+  if (s != SRM_OK) return s;
+  if (trials < 1) return fail(SRM_E_ARG, "trials must be >= 1");
+  const srm_tuning start = c->tune;
+  const int it0 = c->iters;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OR_FAIL(hipEventCreate(&e0));
+  HIP_OR_FAIL(hipEventCreate(&e1));
+  HIP_OR_FAIL(copy_state_regions(c, true));
+  const auto all = tuning_candidates(c->p);
+  // Coordinate search: the sweep's shapes at the default reduction, then the
+  // reduction's shapes at the best sweep.
+  srm_tuning bt = start;
+  double bms = 1e300;
+  int bad = 0;
+  auto trial = [&](const srm_tuning& t) -> srm_status {
+    double ms = 0.0;
+    const srm_status st = time_tuning(c, t, trials, e0, e1, &ms, &bad);
+    if (st != SRM_OK || bad) return st;
+    if (ms < bms) {
+      bms = ms;
+      bt = t;
+    }
+    return SRM_OK;
+  };
+  const int r0 = default_tuning(c->p).reduce_wgs;
+  for (const auto& t : all) {
+    if (t.reduce_wgs != r0) continue;
+    s = trial(t);
+    if (s != SRM_OK || bad) break;
+  }
+  if (s == SRM_OK && !bad) {
+    const srm_tuning sw = bt;
+    for (const auto& t : all) {
+      if (t.reduce_wgs == r0 || t.sweep_kernel != sw.sweep_kernel || t.sweep_wgs != sw.sweep_wgs ||
+          t.chunk_rows != sw.chunk_rows || t.mphase_rounds != sw.mphase_rounds)
+        continue;
+      s = trial(t);
+      if (s != SRM_OK || bad) break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->iters = it0;
+  c->a_valid = false;  // the trials overwrote the A records
+  if (s != SRM_OK || bad) {
+    const std::string msg = g_err;
+    (void)apply_tuning(c, start);
+    g_err = msg;
+    if (s != SRM_OK) return s;
+    return fail((srm_status)bad, "a trial iteration raised a numeric failure (status %d); "
+                "the state is unchanged", bad);
+  }
+  s = apply_tuning(c, bt);
+  if (s != SRM_OK) return s;
+  tune_cache_store(c, bt, bms);
+  if (best) *best = bt;
+  if (best_ms) *best_ms = bms;
   return SRM_OK;
 }
 

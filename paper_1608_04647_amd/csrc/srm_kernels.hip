@@ -106,6 +106,51 @@ __device__ __forceinline__ uint2 bload8(__amdgpu_buffer_rsrc_t r, int voff, int 
   return make_uint2(v.x, v.y);
 }
 
+// LDS read with a transpose (gfx950 ds_read_b64_tr_b16): in each group of
+// 16 lanes, lane 4 r + q supplies four consecutive 16-bit values that become
+// positions 4 q .. 4 q + 3 of row r (r, q = 0..3), and lane i receives
+// position i of rows 0..3.  p is this lane's LDS byte address.
+typedef short v4s __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4s ds_tr16(const char* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) v4s*)(p));
+}
+// Direct load of 16 bytes per lane from a buffer into LDS: lane j's bytes
+// land at lds + 16 j (lds wave-uniform).  Written as one asm statement (M0 is
+// set in it) so that the compiler does not guard every later LDS read with a
+// wait for all outstanding loads: the caller waits for these loads itself
+// (s_waitcnt vmcnt) and then synchronises the workgroup before reading.
+// M0 is reserved by the compiler, which sets it right before each of its
+// own uses, so it is left off the clobber list.
+typedef int v4i_rsrc __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4i_rsrc make_rsrc_v4(const void* p, uint32_t bytes) {
+  const uint64_t a = (uint64_t)p;
+  return v4i_rsrc{(int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)bytes, 0x00020000};
+}
+__device__ __forceinline__ void load_lds16(v4i_rsrc r, const void* lds, int voff, int soff) {
+  const uint32_t m = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)(lds));
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+               :: "s"(m), "v"(voff), "s"(r), "s"(soff) : "memory");
+}
+
+// A slice descriptor read through the scalar unit (the table is written
+// before the launch and only read during it): row0 and nrows, wave-uniform.
+// The wait sits in the same statement, so the outputs are complete when the
+// statement ends.
+__device__ __forceinline__ void slice_s(const Slice* p, int64_t& row0, int32_t& nrows) {
+  v4i_rsrc v;
+  asm volatile("s_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p));
+  row0 = (int64_t)(uint32_t)v.x | ((int64_t)(uint32_t)v.y << 32);
+  nrows = v.z;
+}
+
+// Two transposed reads (4 + 4 values) -> one 8-value bf16 operand.
+__device__ __forceinline__ uint4 pack_tr(v4s a, v4s b) {
+  const uint2 x = __builtin_bit_cast(uint2, a), y = __builtin_bit_cast(uint2, b);
+  return make_uint4(x.x, x.y, y.x, y.y);
+}
+
 // Workgroup ids are dealt round-robin to the 8 XCDs; map them so that
 // consecutive logical ids share an XCD (and its L2).
 __device__ __forceinline__ int xcd_remap(int h, int G) {
@@ -654,7 +699,7 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
 // Z_s and G_s per slice equal what the two-pass E-phase forms from
 // A = Xhat S^T; A itself never goes to HBM.
 // ---------------------------------------------------------------------------
-template <int KP, int PREC, int NW>
+template <int KP, int PREC, int NW, int CH>
 __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
   if (a.sc->status) return;
   static_assert(PREC != P_FP32, "one-pass sweep is for the BF16 forms");
@@ -665,11 +710,10 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
   constexpr int NG = (NPAIR + NW - 1) / NW;
   constexpr int LDT = 64 * NW;
   constexpr int NSTEP = LDT / 32;  // 32-TR MFMA steps
-  // Chunk rows: one 16-row block per wave, except with eight waves, where
-  // half of them form A over 64-row chunks.  The smaller chunk keeps the
-  // lines that part 2 reads again within reach of the L2 (measured faster
-  // than splitting the features of a block over two waves).
-  constexpr int CH = (NW == 8) ? 8 * NW : 16 * NW;
+  // Chunk rows CH: one 16-row block per wave (CH = 16 NW), or with eight
+  // waves also 64-row chunks, in which half of them form A: the smaller
+  // chunk keeps the lines that part 2 reads again within reach of the L2.
+  static_assert(CH % 32 == 0 && CH <= 16 * NW, "chunks are whole A records");
   constexpr int NPW = CH / 16;     // waves with part-1 work
   constexpr int NRB = CH / 32;     // A records (32-row blocks) per chunk
   constexpr int D = 4;             // Xhat prefetch depth in part 1
@@ -863,6 +907,263 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
             gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p / NW][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-pass sweep with Xhat staged in LDS (BF16 forms): the same partials as
+// k_fused (Z_s = A_s^T Xhat_s, G_s = A_s^T A_s per slice, A = Xhat S^T never
+// stored), but every 32-row chunk of Xhat is read from HBM exactly once, by
+// direct-to-LDS buffer loads issued one chunk ahead (double buffer), and both
+// uses read it from LDS:
+//  part 1: A[32 rows, KP] = Xhat S^T.  S lives in registers: wave w holds the
+//          S operands of FPW feature blocks (group w % (NB / FPW)) for the TR
+//          part w / (NB / FPW), and forms that part's partial sums for both
+//          16-row tiles, reading each Xhat operand once for its FPW blocks.
+//          The TR parts are added through LDS in a fixed order and rounded
+//          to bf16 hi+lo A records.
+//  part 2: wave w adds A^T Xhat over its 64 TRs and its share of the Gram
+//          tiles.  The rows-as-K operand of Xhat comes from LDS by transposing
+//          reads (ds_read_b64_tr_b16: in each 16-lane group, lane 4r + q
+//          supplies TRs 4q..4q+3 of row r and every lane receives its own TR
+//          of the four rows).
+// LDS records: one 1 KB record per (plane, 16-row tile, 32-TR step), in the
+// matrix-core operand order (lane n + 16 g holds row n, TRs 8g..8g+7), which
+// is also the order a direct load deposits (lane j's 16 bytes at 16 j).
+// Partial sums: one 1 KB slot per (TR part, output), an output being a
+// (feature block, row tile) pair; the wave that finalises an output reads its
+// TR parts' slots and writes the output's A record halves (hi, lo) into the
+// slot of TR part 0, which no other wave reads.
+// ---------------------------------------------------------------------------
+template <int KP, int PREC, int NW>
+__global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
+  if (a.sc->status) return;  // no kernel of this launch raises it: uniform
+  static_assert(PREC != P_FP32, "one-pass sweep is for the BF16 forms");
+  constexpr bool X2 = PREC == P_BF16X2;
+  constexpr int PL = X2 ? 2 : 1;
+  constexpr int NB = KP / 16;
+  constexpr int LDT = 64 * NW;
+  constexpr int NSTEP = LDT / 32;
+  constexpr int FPW = (NB % 2 == 0) ? 2 : NB;  // feature blocks per part-1 wave
+  constexpr int NFG = NB / FPW;                // feature groups
+  static_assert(NW % NFG == 0, "feature groups must divide the waves");
+  constexpr int TP = NW / NFG;         // TR parts of part 1
+  static_assert(NSTEP % TP == 0, "TR parts are whole 32-TR steps");
+  constexpr int SPW = NSTEP / TP;      // part-1 steps per wave
+  constexpr int NOUT = 2 * NB;         // outputs: (feature block, row tile)
+  constexpr int NREC = PL * 2 * NSTEP; // records per 32-row chunk
+  constexpr int LPW = NREC / NW;       // direct loads per wave per chunk
+  static_assert(NREC % NW == 0 && LPW <= 15, "");
+  constexpr int NPAIR = NB * (NB + 1) / 2;
+  constexpr int NG = (NPAIR + NW - 1) / NW;
+  __shared__ uint4 Xs[2][NREC][64];
+  __shared__ uint4 Pa[TP][NOUT][64];  // [TR part][output][lane]; A records in part 0
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int fg = wave % NFG, tp = wave / NFG;
+  const uint16_t* XH = (const uint16_t*)a.xh;
+  const uint16_t* XL = (const uint16_t*)a.xl;
+
+  const int sb = a.range_slice[blockIdx.x], se = a.range_slice[blockIdx.x + 1];
+  if (sb >= se) return;
+
+  // S operands of this wave's feature blocks and TR part (S records
+  // [step][feature block][lane]).
+  uint4 sh[FPW][SPW], sl[FPW][SPW];
+#pragma unroll
+  for (int f = 0; f < FPW; ++f)
+#pragma unroll
+    for (int j = 0; j < SPW; ++j) {
+      const int st = tp * SPW + j, fb = fg * FPW + f;
+      sh[f][j] = ((const uint4*)a.sh)[(st * NB + fb) * 64 + lane];
+      sl[f][j] = ((const uint4*)a.sl)[(st * NB + fb) * 64 + lane];
+    }
+
+  // Direct loads of the chunk starting at global row r0 into buffer b:
+  // wave w fetches records w LPW .. w LPW + LPW - 1.
+  const int voff_lane = (n * LDT + 8 * g) * 2;
+  auto issue = [&](int64_t r0, int b) {
+    const uint32_t cbytes = 32u * LDT * 2u;
+    const v4i_rsrc RH = make_rsrc_v4(XH + r0 * LDT, cbytes);
+    const v4i_rsrc RL = make_rsrc_v4(XL + r0 * LDT, cbytes);
+#pragma unroll
+    for (int j = 0; j < LPW; ++j) {
+      const int r = wave * LPW + j;
+      const int pl = r / (2 * NSTEP), rb = (r / NSTEP) & 1, st = r % NSTEP;
+      const int so = (16 * rb * LDT + 32 * st) * 2;
+      load_lds16(pl ? RL : RH, &Xs[b][r][0], voff_lane, so);
+    }
+  };
+  // record index of (plane, 16-row tile, step)
+  auto rec = [](int pl, int rb, int st) { return (pl * 2 + rb) * NSTEP + st; };
+
+  f32x4 zacc[NB][4];
+  f32x4 gacc[NG];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zacc[jb][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int s = sb, cr = 0, buf = 0;
+  int64_t row0;
+  int32_t nrows;
+  slice_s(a.slices + s, row0, nrows);
+  issue(row0, 0);
+  // Part-2 transposing reads: lane 4r + q of group g reads TRs 4q..4q+3 of
+  // rows 4g + r (first read) and 16 + 4g + r (second read) of a 16-TR tile.
+  const int tr_r = (lane & 15) >> 2, tr_q = lane & 3;
+  for (;;) {
+    int ns = s, ncr = cr + 32;
+    if (ncr >= nrows) { ns = s + 1; ncr = 0; }
+    const bool has_next = ns < se;
+    int64_t nrow0 = row0;
+    int32_t nnrows = nrows;
+    if (has_next && ns != s) slice_s(a.slices + ns, nrow0, nnrows);
+    if (has_next) {
+      issue(nrow0 + ncr, buf ^ 1);
+      // this chunk's loads are the older ones: leave the LPW just issued
+      __builtin_amdgcn_s_waitcnt((LPW & 15) | (7 << 4) | (15 << 8));
+    } else {
+      __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
+    }
+    __syncthreads();
+    // ---- part 1: partial A over this wave's TR part, its feature blocks
+    {
+      f32x4 acc[FPW][2];
+#pragma unroll
+      for (int f = 0; f < FPW; ++f)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) acc[f][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < SPW; ++j) {
+        const int st = tp * SPW + j;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const uint4 xa = Xs[buf][rec(0, m, st)][lane];
+          uint4 xb;
+          if constexpr (X2) xb = Xs[buf][rec(1, m, st)][lane];
+#pragma unroll
+          for (int f = 0; f < FPW; ++f) {
+            acc[f][m] = mfma_bf16(xa, sh[f][j], acc[f][m]);
+            acc[f][m] = mfma_bf16(xa, sl[f][j], acc[f][m]);
+            if constexpr (X2) acc[f][m] = mfma_bf16(xb, sh[f][j], acc[f][m]);
+          }
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < FPW; ++f)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+          Pa[tp][2 * (fg * FPW + f) + m][lane] =
+              make_uint4(__float_as_uint(acc[f][m][0]), __float_as_uint(acc[f][m][1]),
+                         __float_as_uint(acc[f][m][2]), __float_as_uint(acc[f][m][3]));
+      __syncthreads();
+      // Output o = 2 fb + m (feature block fb, row tile m): its TR parts
+      // summed in order, rounded to hi + lo and written over its TR-part-0
+      // slot as (hi pair, lo pair): lane holds A[16 m + 4 g + i][16 fb + n],
+      // half m of the A record of block fb.
+      for (int o = wave; o < NOUT; o += NW) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < TP; ++p) {
+          const uint4 u = Pa[p][o][lane];
+          v[0] += __uint_as_float(u.x);
+          v[1] += __uint_as_float(u.y);
+          v[2] += __uint_as_float(u.z);
+          v[3] += __uint_as_float(u.w);
+        }
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          h[i] = f2bf(v[i]);
+          l[i] = f2bf(v[i] - bf2f(h[i]));
+        }
+        Pa[0][o][lane] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                                    l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+      }
+    }
+    __syncthreads();
+    // ---- part 2: Z[:, 64 w + 16 q + n] += A^T Xhat, Gram tiles
+    {
+      uint4 ah[NB], al[NB];
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        const uint4 t0 = Pa[0][2 * jb][lane], t1 = Pa[0][2 * jb + 1][lane];
+        ah[jb] = make_uint4(t0.x, t0.y, t1.x, t1.y);
+        al[jb] = make_uint4(t0.z, t0.w, t1.z, t1.w);
+      }
+      const char* xb0 = (const char*)&Xs[buf][0][0];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = 64 * wave + 16 * q + 4 * tr_q;  // first of this lane's 4 TRs
+        const int st = t >> 5, gq = (t & 31) >> 3, half = (t & 7) >> 2;
+        const int in_rec = ((4 * g + tr_r) + 16 * gq) * 16 + 8 * half;
+        uint4 bh, bl;
+        {
+          const v4s r1 = ds_tr16(xb0 + rec(0, 0, st) * 1024 + in_rec);
+          const v4s r2 = ds_tr16(xb0 + rec(0, 1, st) * 1024 + in_rec);
+          bh = pack_tr(r1, r2);
+        }
+        if constexpr (X2) {
+          const v4s r1 = ds_tr16(xb0 + rec(1, 0, st) * 1024 + in_rec);
+          const v4s r2 = ds_tr16(xb0 + rec(1, 1, st) * 1024 + in_rec);
+          bl = pack_tr(r1, r2);
+        }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          zacc[jb][q] = mfma_bf16(ah[jb], bh, zacc[jb][q]);
+          zacc[jb][q] = mfma_bf16(al[jb], bh, zacc[jb][q]);
+          if constexpr (X2) zacc[jb][q] = mfma_bf16(ah[jb], bl, zacc[jb][q]);
+        }
+      }
+      int p = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NB; ++j2, ++p)
+          if ((p % NW) == wave) {
+            gacc[p / NW] = mfma_bf16(ah[j1], ah[j2], gacc[p / NW]);
+            gacc[p / NW] = mfma_bf16(ah[j1], al[j2], gacc[p / NW]);
+            gacc[p / NW] = mfma_bf16(al[j1], ah[j2], gacc[p / NW]);
+            gacc[p / NW] = mfma_bf16(al[j1], al[j2], gacc[p / NW]);
+          }
+    }
+    if (ns != s || !has_next) {
+      // the slice is complete: lane holds Z[16 jb + 4 g + i][64 w + 16 q + n]
+      float* zp = a.zpart + (int64_t)s * KP * LDT + 64 * wave + n;
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            zp[(16 * jb + 4 * g + i) * LDT + 16 * q] = zacc[jb][q][i];
+            zacc[jb][q][i] = 0.f;
+          }
+      float* gp = a.gpart + (int64_t)s * KP * KP;
+      int p = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NB; ++j2, ++p)
+          if ((p % NW) == wave)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p / NW][i];
+              gacc[p / NW][i] = 0.f;
+            }
+    }
+    // every wave is done with this buffer and the A records
+    __syncthreads();
+    if (!has_next) break;
+    s = ns;
+    cr = ncr;
+    row0 = nrow0;
+    nrows = nnrows;
+    buf ^= 1;
   }
 }
 
@@ -2200,23 +2501,77 @@ hipError_t launch_transform(hipStream_t st, int kp, int nsplit, const TArgs& a,
 bool fused_supported(int kp, int prec, int64_t ldt) {
   return prec != P_FP32 && kp <= 64 && ldt <= 512 && ldt % 128 == 0;
 }
-hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
+// Chunk rows the register-ring sweep supports for ldt (16 ldt / 64, and 64
+// with eight waves).
+bool fused_chunk_ok(int64_t ldt, int chunk) {
+  const int nw = (int)(ldt / 64);
+  return chunk == 16 * nw || (nw == 8 && chunk == 64);
+}
+hipError_t launch_fused(hipStream_t st, int kp, int prec, int64_t ldt, int grid, int chunk,
                         const FusedArgs& a) {
   const int nw = (int)(ldt / 64);
-#define SRM_FUSED_NW(NWV)                                                       \
-  case NWV:                                                                     \
-    SRM_KP_SWITCH(kp, if constexpr (KP <= 64) {                                 \
-      if (prec == P_BF16)                                                       \
-        hipLaunchKernelGGL((k_fused<KP, P_BF16, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
-      else                                                                      \
-        hipLaunchKernelGGL((k_fused<KP, P_BF16X2, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
-    });                                                                         \
-    break;
+  if (!fused_chunk_ok(ldt, chunk)) return hipErrorInvalidValue;
+#define SRM_FUSED_LAUNCH(NWV, CHV)                                                \
+    SRM_KP_SWITCH(kp, if constexpr (KP <= 64) {                                   \
+      if (prec == P_BF16)                                                         \
+        hipLaunchKernelGGL((k_fused<KP, P_BF16, NWV, CHV>), dim3(grid), dim3(NWV * 64), 0, \
+                           st, a);                                                \
+      else                                                                        \
+        hipLaunchKernelGGL((k_fused<KP, P_BF16X2, NWV, CHV>), dim3(grid), dim3(NWV * 64), 0, \
+                           st, a);                                                \
+    });
   switch (nw) {
-    SRM_FUSED_NW(2) SRM_FUSED_NW(4) SRM_FUSED_NW(6) SRM_FUSED_NW(8)
+    case 2: SRM_FUSED_LAUNCH(2, 32) break;
+    case 4: SRM_FUSED_LAUNCH(4, 64) break;
+    case 6: SRM_FUSED_LAUNCH(6, 96) break;
+    case 8:
+      if (chunk == 64) { SRM_FUSED_LAUNCH(8, 64) } else { SRM_FUSED_LAUNCH(8, 128) }
+      break;
     default: return hipErrorInvalidValue;
   }
-#undef SRM_FUSED_NW
+#undef SRM_FUSED_LAUNCH
+  return hipGetLastError();
+}
+
+// LDS bytes of k_staged<KP, PREC, NW> (0 when its wave split does not
+// apply): two chunk buffers of PL x 2 x 2 NW records and TP x 2 NB slots.
+constexpr int staged_lds(int kp, int prec, int nw) {
+  const int nb = kp / 16, fpw = (nb % 2 == 0) ? 2 : nb, nfg = nb / fpw;
+  if (nb < 1 || nw % nfg != 0) return 0;
+  const int pl = prec == P_BF16X2 ? 2 : 1;
+  return (2 * pl * 2 * 2 * nw + (nw / nfg) * 2 * nb) * 1024;
+}
+bool staged_supported(int kp, int prec, int64_t ldt) {
+  const int nw = (int)(ldt / 64);
+  const int lds = staged_lds(kp, prec, nw);
+  return fused_supported(kp, prec, ldt) && lds > 0 && lds <= 160 * 1024;
+}
+hipError_t launch_staged(hipStream_t st, int kp, int prec, int64_t ldt, int grid,
+                         const FusedArgs& a) {
+  const int nw = (int)(ldt / 64);
+#define SRM_STAGED_NW(NWV)                                                       \
+  case NWV:                                                                     \
+    SRM_KP_SWITCH(kp, if constexpr (KP <= 64) {                                 \
+      if constexpr (staged_lds(KP, P_BF16, NWV) > 0 &&                          \
+                    staged_lds(KP, P_BF16, NWV) <= 160 * 1024)                  \
+        if (prec == P_BF16) {                                                   \
+          hipLaunchKernelGGL((k_staged<KP, P_BF16, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
+          break;                                                                \
+        }                                                                       \
+      if constexpr (staged_lds(KP, P_BF16X2, NWV) > 0 &&                        \
+                    staged_lds(KP, P_BF16X2, NWV) <= 160 * 1024)                \
+        if (prec == P_BF16X2) {                                                 \
+          hipLaunchKernelGGL((k_staged<KP, P_BF16X2, NWV>), dim3(grid), dim3(NWV * 64), 0, st, a); \
+          break;                                                                \
+        }                                                                       \
+      return hipErrorInvalidValue;                                              \
+    } else { return hipErrorInvalidValue; });                                   \
+    break;
+  switch (nw) {
+    SRM_STAGED_NW(2) SRM_STAGED_NW(4) SRM_STAGED_NW(6) SRM_STAGED_NW(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef SRM_STAGED_NW
   return hipGetLastError();
 }
 

@@ -35,8 +35,9 @@ SRM_OK, SRM_E_ARG, SRM_E_WORKSPACE, SRM_E_HIP, SRM_E_RANK, SRM_E_NOTPD, \
 STATUS_NAMES = {0: "SRM_OK", 1: "SRM_E_ARG", 2: "SRM_E_WORKSPACE", 3: "SRM_E_HIP",
                 4: "SRM_E_RANK", 5: "SRM_E_NOTPD", 6: "SRM_E_NONFINITE", 7: "SRM_E_STATE"}
 PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2}
-SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE, SRM_GRAM = \
-    1, 2, 4, 8, 16, 32
+SRM_NO_GRAPH, SRM_NO_W0_CHECK, SRM_TWO_PASS, SRM_X_HOST, SRM_ZSCORE, SRM_GRAM, \
+    SRM_AUTOTUNE = 1, 2, 4, 8, 16, 32, 64
+KERNELS = {0: "ring", 1: "staged"}
 
 
 SWEEPS = {0: "one_pass", 1: "two_pass", 2: "gram"}
@@ -53,6 +54,24 @@ class SrmInfo(ctypes.Structure):
                 ("k_padded", ctypes.c_int32), ("n_ranges", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
                 ("ldt", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class SrmTuning(ctypes.Structure):
+    _fields_ = [("sweep_kernel", ctypes.c_int32), ("sweep_wgs", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int32), ("reduce_wgs", ctypes.c_int32),
+                ("mphase_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    FIELDS = ("sweep_kernel", "sweep_wgs", "chunk_rows", "reduce_wgs", "mphase_rounds")
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f in self.FIELDS}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "SrmTuning":
+        t = cls()
+        for f in cls.FIELDS:
+            setattr(t, f, int(d[f]))
+        return t
 
 
 _P = ctypes.c_void_p
@@ -83,6 +102,11 @@ _sigs = {
     "srm_set_state": (ctypes.c_int, [_P, _P, _SZ]),
     "srm_get_loglik": (ctypes.c_int, [_P, _DP, _I32, ctypes.POINTER(_I32)]),
     "srm_iterations": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
+    "srm_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(SrmTuning)]),
+    "srm_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(SrmTuning)]),
+    "srm_tuning_candidates": (ctypes.c_int, [_P, ctypes.POINTER(SrmTuning), _I32,
+                                             ctypes.POINTER(_I32)]),
+    "srm_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(SrmTuning), _DP]),
     "srm_last_error": (ctypes.c_char_p, []),
     "srm_free": (None, [_P]),
 }
@@ -138,8 +162,9 @@ class SRM:
 
     def __init__(self, X, k: int, prec: str = "fp32", W0=None, flags: int = 0,
                  seed: int = 0, stream_from_host: bool = False, zscore: bool = False,
-                 gram: bool = False):
-        torch = self._setup(flags, stream_from_host, zscore, gram)
+                 gram: bool = False, autotune: bool = False):
+        torch = self._setup(flags | (SRM_AUTOTUNE if autotune else 0), stream_from_host,
+                            zscore, gram)
         xs = [self._prep_x(x) for x in X]
         self._open([int(x.shape[0]) for x in xs], int(xs[0].shape[1]), k, prec)
         w0 = None if W0 is None else [None if w is None else
@@ -158,10 +183,11 @@ class SRM:
 
     @classmethod
     def begin(cls, v, t: int, k: int, prec: str = "fp32", flags: int = 0, seed: int = 0,
-              stream_from_host: bool = False, zscore: bool = False, gram: bool = False):
+              stream_from_host: bool = False, zscore: bool = False, gram: bool = False,
+              autotune: bool = False):
         """A fit awaiting its subjects (srm_init_begin)."""
         self = cls.__new__(cls)
-        self._setup(flags, stream_from_host, zscore, gram)
+        self._setup(flags | (SRM_AUTOTUNE if autotune else 0), stream_from_host, zscore, gram)
         self._open([int(x) for x in v], int(t), k, prec)
         ctx = _P()
         self._t0 = time.perf_counter()
@@ -182,7 +208,9 @@ class SRM:
 
     def end(self):
         """srm_init_end: every subject ingested; runs the first E-step."""
+        t0 = time.perf_counter()
         _check(_lib.srm_init_end(self._ctx))
+        self.end_seconds = time.perf_counter() - t0
         self.init_seconds = time.perf_counter() - self._t0
         return self
 
@@ -227,6 +255,30 @@ class SRM:
         return {"sweep": SWEEPS.get(inf.sweep, inf.sweep), "graph": bool(inf.graph),
                 "k_padded": inf.k_padded, "n_ranges": inf.n_ranges, "n_slices": inf.n_slices,
                 "ldt": inf.ldt, "workspace_bytes": inf.workspace_bytes}
+
+    # -- launch shapes -----------------------------------------------------
+    def tuning(self) -> dict:
+        t = SrmTuning()
+        _check(_lib.srm_get_tuning(self._ctx, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, d: dict):
+        _check(_lib.srm_set_tuning(self._ctx, ctypes.byref(SrmTuning.from_dict(d))))
+
+    def tuning_candidates(self) -> list:
+        n = _I32()
+        _check(_lib.srm_tuning_candidates(self._ctx, None, 0, ctypes.byref(n)))
+        arr = (SrmTuning * max(n.value, 1))()
+        _check(_lib.srm_tuning_candidates(self._ctx, arr, n.value, ctypes.byref(n)))
+        return [arr[i].as_dict() for i in range(n.value)]
+
+    def autotune(self, trials: int = 2):
+        """srm_autotune: times the candidates, keeps the fastest; returns
+        (shape, ms per iteration)."""
+        t = SrmTuning()
+        ms = ctypes.c_double()
+        _check(_lib.srm_autotune(self._ctx, int(trials), ctypes.byref(t), ctypes.byref(ms)))
+        return t.as_dict(), ms.value
 
     # -- iteration ---------------------------------------------------------
     def fit(self, n_iter: int) -> np.ndarray:

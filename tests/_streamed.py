@@ -24,7 +24,9 @@ def gram_summaries(w: synth.Workload, seed: int = 0, threads: Optional[int] = No
     one thread per worker; at most 2 x threads subjects are in flight, so
     host memory holds a few subjects of X at a time."""
     g = synth.draw_globals(w, seed)
-    nthr = threads or _threads()
+    # each worker holds a subject in float32 and its demeaned float64 copy
+    per = float(w.v_hi) * w.t * 16.0
+    nthr = threads or max(1, min(_threads(), int(96e9 // per)))
 
     def one(i):
         X = synth.subject(w, g, i, seed)

@@ -128,6 +128,13 @@ def test_calls_on_null_context():
     n = ctypes.c_size_t(0)
     assert lib.srm_get_state(None, None, ctypes.byref(n)) == srm.SRM_E_ARG
     assert lib.srm_set_state(None, None, 0) == srm.SRM_E_ARG
+    assert lib.srm_transform_static(None, 0, None, 1, None) == srm.SRM_E_ARG
+    t = srm.SrmTuning()
+    cnt = ctypes.c_int32()
+    assert lib.srm_get_tuning(None, ctypes.byref(t)) == srm.SRM_E_ARG
+    assert lib.srm_set_tuning(None, ctypes.byref(t)) == srm.SRM_E_ARG
+    assert lib.srm_tuning_candidates(None, None, 0, ctypes.byref(cnt)) == srm.SRM_E_ARG
+    assert lib.srm_autotune(None, 2, None, None) == srm.SRM_E_ARG
     lib.srm_free(None)
 
 

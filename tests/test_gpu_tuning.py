@@ -1,0 +1,137 @@
+"""Launch shapes (srm_tuning): every candidate the autotuner can pick reaches
+the oracle's EM iterate within the bar, on the one-pass sweep (register-ring
+and LDS-staged kernels, both BF16 forms, K paddings 16, 32, 64), the two-pass
+sweep and the sample-space iteration; srm_autotune leaves the carried state
+unchanged and keeps a candidate; SRM_AUTOTUNE reads and writes the cache."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_04647_amd import synth
+
+from _parity import compare, stored_values
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp32": 1e-4, "bf16x2": 1e-3, "bf16": 1e-3}
+
+
+def _srm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_04647_amd import srm
+    return srm
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    # the batched workload's shape (500 TRs, k = 50: K padding 64, eight
+    # waves), several chunks and slices per row range
+    "wide2": synth.Workload("wide2", 3, 20000, 30000, 500, 50, 4, sigma_lo=0.5, sigma_hi=2.0),
+    # K padding 32 with six waves (t = 300): three TR parts in the staged kernel
+    "k20": synth.Workload("k20", 4, 700, 2600, 300, 20, 4, sigma_lo=0.5, sigma_hi=2.0),
+    # K padding 64 with four waves (t = 200): one TR part in the staged kernel
+    "k50t200": synth.Workload("k50t200", 3, 300, 2000, 200, 50, 4, sigma_lo=0.5,
+                              sigma_hi=2.0),
+    # K padding 16 with two waves (t = 70), ragged subjects
+    "ragged": synth.Workload("ragged", 5, 33, 250, 70, 7, 6),
+    # two-pass sweep (FP32 storage), many ranges and slices
+    "slices": synth.Workload("slices", 6, 3000, 9000, 300, 20, 4, sigma_lo=0.5, sigma_hi=2.0),
+}
+
+
+def _oracle(d, w, prec):
+    if prec == "bf16":
+        Xq = [stored_values(x, prec) for x in d["X"]]
+        return oracle.em_fit(Xq, w.k, w.n_iter, d["W0"], final_loglik=True, demeaned=True)
+    return oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"], final_loglik=True)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case,prec,gram", [
+    ("wide2", "bf16x2", False), ("wide2", "bf16", False), ("k20", "bf16x2", False),
+    ("k50t200", "bf16x2", False), ("ragged", "bf16", False), ("slices", "fp32", False), ("slices", "bf16x2", True)])
+def test_every_candidate_meets_the_bar(case, prec, gram):
+    srm = _srm()
+    w = CASES[case]
+    d = synth.generate(w, seed=21)
+    ora = _oracle(d, w, prec)
+    g0 = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"], gram=gram)
+    cands = g0.tuning_candidates()
+    sweep = g0.info()["sweep"]
+    g0.close()
+    kernels = sorted({c["sweep_kernel"] for c in cands})
+    _say(f"[case] {case}/{prec} sweep={sweep}: {len(cands)} candidates, kernels {kernels}")
+    if sweep == "one_pass":
+        assert kernels == [0, 1], "the staged kernel applies to these shapes"
+    worst = {}
+    for t in cands:
+        g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"], gram=gram)
+        g.set_tuning(t)
+        assert g.tuning() == t
+        g.fit(w.n_iter)
+        assert g.info()["graph"]
+        e = compare(g, ora, w.n_subjects)
+        for key in ("S", "W", "rho2", "Sigma_s", "ll"):
+            worst[key] = max(worst.get(key, 0.0), e[key])
+        bar = BAR[prec]
+        assert e["S"] <= bar and e["W"] <= bar and e["rho2"] <= bar and e["Sigma_s"] <= bar, \
+            (t, e)
+        assert e["ll"] <= (1e-6 if prec == "fp32" else 1e-4), (t, e)
+        g.close()
+    _say(f"[errors] {case}/{prec} worst over {len(cands)} shapes: " +
+         ", ".join(f"{k}={v:.2e}" for k, v in worst.items()))
+
+
+def test_set_tuning_refuses_other_shapes():
+    srm = _srm()
+    w = CASES["ragged"]
+    d = synth.generate(w, seed=2)
+    g = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"])
+    t = g.tuning()
+    for bad in (dict(t, sweep_wgs=300), dict(t, reduce_wgs=128), dict(t, sweep_kernel=7),
+                dict(t, chunk_rows=48)):
+        with pytest.raises(srm.SRMError) as ei:
+            g.set_tuning(bad)
+        assert ei.value.status == srm.SRM_E_ARG
+    assert g.tuning() == t
+
+
+def test_autotune_keeps_the_state_and_a_candidate(tmp_path, monkeypatch):
+    """srm_autotune restores the carried state after its trials; the shape it
+    keeps is a candidate and the fit continues to the bar.  With
+    SRM_AUTOTUNE a second context of the same problem takes the cached shape
+    without timing trials."""
+    srm = _srm()
+    w = CASES["wide2"]
+    d = synth.generate(w, seed=4)
+    cache = tmp_path / "tune.tsv"
+    monkeypatch.setenv("SRM_TUNE_CACHE", str(cache))
+    g = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"])
+    g.fit(1)
+    before = g.get_state()
+    best, ms = g.autotune(trials=2)
+    _say(f"[tuning] wide2 bf16x2: best {best} at {ms:.3f} ms per iteration")
+    assert best in g.tuning_candidates() and g.tuning() == best and ms > 0
+    assert g.get_state() == before and g.iterations() == 1
+    g.fit(w.n_iter - 1)
+    ora = oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"], final_loglik=True)
+    e = compare(g, ora, w.n_subjects)
+    assert e["S"] <= 1e-3 and e["W"] <= 1e-3 and e["rho2"] <= 1e-3
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    h = srm.SRM(d["X"], w.k, prec="bf16x2", W0=d["W0"], autotune=True)
+    assert h.tuning() == best
+    assert len(cache.read_text().splitlines()) == 1  # read, not re-tuned
+    # a different problem tunes itself and appends its own line
+    d2 = synth.generate(w, seed=5)
+    srm.SRM(d2["X"], w.k, prec="bf16x2", W0=d2["W0"], autotune=True)
+    assert len(cache.read_text().splitlines()) == 2
