@@ -932,8 +932,9 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
 // is also the order a direct load deposits (lane j's 16 bytes at 16 j).
 // Partial sums: one 1 KB slot per (TR part, output), an output being a
 // (feature block, row tile) pair; the wave that finalises an output reads its
-// TR parts' slots and writes the output's A record halves (hi, lo) into the
-// slot of TR part 0, which no other wave reads.
+// TR parts' slots and writes the output's half of the A record into the slot
+// of TR part 0, which no other wave reads: the 64 lanes' hi pairs, then their
+// lo pairs.
 // ---------------------------------------------------------------------------
 template <int KP, int PREC, int NW>
 __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
@@ -981,15 +982,21 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
     }
 
   // Direct loads of the chunk starting at global row r0 into buffer b:
-  // wave w fetches records w LPW .. w LPW + LPW - 1.
+  // wave w fetches records w LPW .. w LPW + LPW - 1, in NGRP groups issued
+  // at points spread over the matrix-core work of the previous chunk (a wave
+  // whose load cannot enter the memory pipeline stalls at the issue: one
+  // burst of all loads would hold every wave up at once, and a stall in a
+  // phase without matrix work would hold up the workgroup's barrier).
+  constexpr int NGRP = (LPW % 4 == 0) ? 4 : ((LPW % 2 == 0) ? 2 : 1);
+  constexpr int LPG = LPW / NGRP;  // loads per group
   const int voff_lane = (n * LDT + 8 * g) * 2;
-  auto issue = [&](int64_t r0, int b) {
+  auto issue = [&](int64_t r0, int b, int grp) {
     const uint32_t cbytes = 32u * LDT * 2u;
     const v4i_rsrc RH = make_rsrc_v4(XH + r0 * LDT, cbytes);
     const v4i_rsrc RL = make_rsrc_v4(XL + r0 * LDT, cbytes);
 #pragma unroll
-    for (int j = 0; j < LPW; ++j) {
-      const int r = wave * LPW + j;
+    for (int jj = 0; jj < LPG; ++jj) {
+      const int r = wave * LPW + grp * LPG + jj;
       const int pl = r / (2 * NSTEP), rb = (r / NSTEP) & 1, st = r % NSTEP;
       const int so = (16 * rb * LDT + 32 * st) * 2;
       load_lds16(pl ? RL : RH, &Xs[b][r][0], voff_lane, so);
@@ -1011,7 +1018,8 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
   int64_t row0;
   int32_t nrows;
   slice_s(a.slices + s, row0, nrows);
-  issue(row0, 0);
+#pragma unroll
+  for (int grp = 0; grp < NGRP; ++grp) issue(row0, 0, grp);
   // Part-2 transposing reads: lane 4r + q of group g reads TRs 4q..4q+3 of
   // rows 4g + r (first read) and 16 + 4g + r (second read) of a 16-TR tile.
   const int tr_r = (lane & 15) >> 2, tr_q = lane & 3;
@@ -1022,14 +1030,13 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
     int64_t nrow0 = row0;
     int32_t nnrows = nrows;
     if (has_next && ns != s) slice_s(a.slices + ns, nrow0, nnrows);
-    if (has_next) {
-      issue(nrow0 + ncr, buf ^ 1);
-      // this chunk's loads are the older ones: leave the LPW just issued
-      __builtin_amdgcn_s_waitcnt((LPW & 15) | (7 << 4) | (15 << 8));
-    } else {
-      __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
-    }
+    const int64_t nr0 = nrow0 + ncr;  // the next chunk's first row
+    // This chunk's loads (issued during the previous one) have landed, for
+    // every wave after the barrier; it also marks every wave done with the
+    // previous chunk, whose buffer the next chunk's loads then refill.
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
     __syncthreads();
+    if (has_next) issue(nr0, buf ^ 1, 0);
     // ---- part 1: partial A over this wave's TR part, its feature blocks
     {
       f32x4 acc[FPW][2];
@@ -1052,6 +1059,7 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
             if constexpr (X2) acc[f][m] = mfma_bf16(xb, sh[f][j], acc[f][m]);
           }
         }
+        if (NGRP > 1 && has_next && j == SPW / 2) issue(nr0, buf ^ 1, 1);
       }
 #pragma unroll
       for (int f = 0; f < FPW; ++f)
@@ -1066,14 +1074,16 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
       // slot as (hi pair, lo pair): lane holds A[16 m + 4 g + i][16 fb + n],
       // half m of the A record of block fb.
       for (int o = wave; o < NOUT; o += NW) {
+        uint4 u[TP];  // every TR part's slot read before any is used
+#pragma unroll
+        for (int p = 0; p < TP; ++p) u[p] = Pa[p][o][lane];
         float v[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int p = 0; p < TP; ++p) {
-          const uint4 u = Pa[p][o][lane];
-          v[0] += __uint_as_float(u.x);
-          v[1] += __uint_as_float(u.y);
-          v[2] += __uint_as_float(u.z);
-          v[3] += __uint_as_float(u.w);
+          v[0] += __uint_as_float(u[p].x);
+          v[1] += __uint_as_float(u[p].y);
+          v[2] += __uint_as_float(u[p].z);
+          v[3] += __uint_as_float(u[p].w);
         }
         uint32_t h[4], l[4];
 #pragma unroll
@@ -1081,19 +1091,26 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
           h[i] = f2bf(v[i]);
           l[i] = f2bf(v[i] - bf2f(h[i]));
         }
-        Pa[0][o][lane] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
-                                    l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+        uint2* dst = (uint2*)&Pa[0][o][0];  // hi pairs, then lo pairs
+        dst[lane] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        dst[64 + lane] = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
       }
     }
+    if (NGRP > 2 && has_next) issue(nr0, buf ^ 1, 2);
     __syncthreads();
     // ---- part 2: Z[:, 64 w + 16 q + n] += A^T Xhat, Gram tiles
     {
+      // A operands of block jb: the hi (lo) pairs of tiles 0 and 1 from the
+      // two outputs' slots, 8 bytes per lane each, straight into the
+      // operand's two register pairs
       uint4 ah[NB], al[NB];
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) {
-        const uint4 t0 = Pa[0][2 * jb][lane], t1 = Pa[0][2 * jb + 1][lane];
-        ah[jb] = make_uint4(t0.x, t0.y, t1.x, t1.y);
-        al[jb] = make_uint4(t0.z, t0.w, t1.z, t1.w);
+        const uint2* t0 = (const uint2*)&Pa[0][2 * jb][0];
+        const uint2* t1 = (const uint2*)&Pa[0][2 * jb + 1][0];
+        const uint2 h0 = t0[lane], h1 = t1[lane], l0 = t0[64 + lane], l1 = t1[64 + lane];
+        ah[jb] = make_uint4(h0.x, h0.y, h1.x, h1.y);
+        al[jb] = make_uint4(l0.x, l0.y, l1.x, l1.y);
       }
       const char* xb0 = (const char*)&Xs[buf][0][0];
 #pragma unroll
@@ -1118,6 +1135,7 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
           zacc[jb][q] = mfma_bf16(al[jb], bh, zacc[jb][q]);
           if constexpr (X2) zacc[jb][q] = mfma_bf16(ah[jb], bl, zacc[jb][q]);
         }
+        if (q == 1 && NGRP > 3 && has_next) issue(nr0, buf ^ 1, 3);
       }
       int p = 0;
 #pragma unroll
@@ -1156,8 +1174,6 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
               gacc[p / NW][i] = 0.f;
             }
     }
-    // every wave is done with this buffer and the A records
-    __syncthreads();
     if (!has_next) break;
     s = ns;
     cr = ncr;
