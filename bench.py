@@ -121,15 +121,26 @@ def open_fit(srm, X, W0, w, v, prec, gram, seed):
     g = srm.SRM.begin([int(x) for x in v], w.t, w.k, prec=prec, stream_from_host=True,
                       flags=srm.SRM_NO_W0_CHECK, gram=gram)
     ingest_s = 0.0
+    last = None
     for i, Xi, W0i in synth.iter_subjects(w, seed, threads=4):
         t1 = time.perf_counter()
         g.ingest(i, Xi, W0i)
         ingest_s += time.perf_counter() - t1
+        last = Xi
         if i % 16 == 15:
             log(f"[bench] {i + 1}/{w.n_subjects} subjects ingested")
     g.end()
     g.ingest_seconds = ingest_s
     g.gen_and_ingest_seconds = time.perf_counter() - t0
+    # For comparison: a plain host-to-device copy of one subject's FP32 rows
+    # from the same kind of (pageable) host memory, no conversion.
+    import torch
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dev = torch.from_numpy(last).to("cuda")
+    torch.cuda.synchronize()
+    g.plain_copy_GBps = last.nbytes / (time.perf_counter() - t1) / 1e9
+    del dev
     return g
 
 
@@ -145,8 +156,14 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
     init_s = g.init_seconds if X is not None else g.ingest_seconds + g.end_seconds
     ingest = None
     if X is None:
+        fp32 = float(np.sum(v)) * w.t * 4
         ingest = {"host_ingest_s": g.ingest_seconds, "generate_and_ingest_s":
-                  g.gen_and_ingest_seconds, "end_s": g.end_seconds}
+                  g.gen_and_ingest_seconds, "end_s": g.end_seconds,
+                  "ingest_GBps": fp32 / g.ingest_seconds / 1e9,
+                  "plain_h2d_copy_GBps": g.plain_copy_GBps,
+                  "note": "srm_ingest of host rows (upload through two staging buffers on a "
+                          "second stream, conversion to the stored format on the compute "
+                          "stream) against a plain pageable copy of one subject"}
     default_shape = g.tuning()
     tuning = {"default": default_shape}
     if table:  # every sweep shape at the default reduction, timed alike
@@ -182,6 +199,8 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
         tuning["default_ms_per_step"] = 1e3 * dt_d / steps
         g.set_tuning(cur)
         log(f"[bench] default shape: {steps / dt_d:.2f} iters/s")
+    info = g.info()  # after the timed srm_fit: which sweep ran, and whether it
+    # replayed the captured graph
     ph = g.profile(prof_steps)
     ph = {k: v_ / prof_steps for k, v_ in ph.items()}
     alg = algorithmic(w, v, prec)
@@ -195,6 +214,7 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
         alg["iter_bytes"], alg["iter_flops"] = alg["gram"]["bytes"], alg["gram"]["flops"]
     res = {"iters_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "init_s": init_s,
            "tuning": tuning, "ingest": ingest,
+           "sweep": info["sweep"], "graph_replayed": info["graph"],
            "hbm_GBps": alg["iter_bytes"] / (dt / steps) / 1e9,
            "phase_ms": ph, "alg": alg, "ll_last": float(ll[-1]) if len(ll) else None}
     return g, res
@@ -369,6 +389,7 @@ def main():
            "hbm_frac": head["hbm_GBps"] / HBM_PEAK_GBS,
            "phase_ms": ph,
            "tuning": head["tuning"],
+           "sweep": head["sweep"], "graph_replayed": head["graph_replayed"],
            "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (head["ms_per_step"] / 1e3) / 1e9,
            "roofline": roof}
     for prec in forms[1:]:
@@ -376,6 +397,7 @@ def main():
         out[f"{prec}_plain" if prec == "fp32" else prec] = {
             "iters_per_s": r["iters_per_s"], "ms_per_step": r["ms_per_step"],
             "hbm_GBps": r["hbm_GBps"], "phase_ms": r["phase_ms"], "tuning": r["tuning"],
+            "sweep": r["sweep"], "graph_replayed": r["graph_replayed"],
             "mfma_TFLOPs": r["alg"]["iter_flops"] / (r["ms_per_step"] / 1e3) / 1e12,
             "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (r["ms_per_step"] / 1e3) / 1e9}
         out[f"speedup_vs_{prec}"] = head["iters_per_s"] / r["iters_per_s"]
