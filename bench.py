@@ -149,10 +149,9 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
     log(f"[bench] init {prec}{' sample-space' if gram else ''}")
     g = open_fit(srm, X, W0, w, v, prec, gram, seed)
     # the library's own initialisation (W0 upload, conversion, G_i for the
-    # sample-space variant, first E-step); the caller's workspace allocation
-    # is not part of it
-    # the library's own initialisation (host ingestion: its ingest calls and
-    # srm_init_end, not the generation of the data)
+    # sample-space variant, first E-step; with host ingestion its ingest calls
+    # and srm_init_end, not the generation of the data); the caller's
+    # workspace allocation is not part of it
     init_s = g.init_seconds if X is not None else g.ingest_seconds + g.end_seconds
     ingest = None
     if X is None:
@@ -238,13 +237,24 @@ def oracle_check(w, seed, snap):
     from _streamed import oracle_fit, oracle_w
     n = snap["iters"]
     t0 = time.perf_counter()
-    ora = oracle_fit(w, n, seed)
+    step = max(1, w.n_subjects // 16)
+
+    def progress(done):
+        if done % step == 0 or done == w.n_subjects:
+            log(f"[oracle] {done}/{w.n_subjects} subjects summarised "
+                f"({time.perf_counter() - t0:.0f} s)")
+
+    ora = oracle_fit(w, n, seed, progress=progress)
+    log(f"[oracle] {n} iterations done ({time.perf_counter() - t0:.0f} s)")
     Q, eS, _ = procrustes(ora["S"], snap["S"])
     eSig = float(np.linalg.norm(ora["Sigma_s"] - Q @ snap["Sigma_s"] @ Q.T)
                  / np.linalg.norm(ora["Sigma_s"]))
     ll_o = np.array(ora["ll"] + [ora["ll_final"]])
     ll_g = snap["ll"][:len(ll_o)]
-    eW = max(proj_err(oracle_w(ora, w, i, seed), Wg) for i, Wg in snap["W"].items())
+    eW = 0.0
+    for i, Wg in snap["W"].items():
+        eW = max(eW, proj_err(oracle_w(ora, w, i, seed), Wg))
+        log(f"[oracle] projector of subject {i} checked ({time.perf_counter() - t0:.0f} s)")
     return {"oracle": f"FP64 Gram form on streamed input, all {w.n_subjects} subjects, "
                       f"{n} iterations from the same W0",
             "S": float(eS), "Sigma_s": eSig,
@@ -392,6 +402,8 @@ def main():
            "sweep": head["sweep"], "graph_replayed": head["graph_replayed"],
            "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (head["ms_per_step"] / 1e3) / 1e9,
            "roofline": roof}
+    if head["ingest"] is not None:
+        out["ingest"] = head["ingest"]
     for prec in forms[1:]:
         r = results[prec]
         out[f"{prec}_plain" if prec == "fp32" else prec] = {
