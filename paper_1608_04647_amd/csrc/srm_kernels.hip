@@ -71,6 +71,20 @@ __device__ __forceinline__ uint32_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint32_t h) {
   return __uint_as_float(h << 16);
 }
+// Two floats to packed bfloat16 bits (a in the low half), round to nearest
+// even by the hardware conversion (v_cvt_pk_bf16_f32); equal to f2bf on
+// finite inputs.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+// hi = bf16(a, b) packed, lo = bf16(a - hi_a, b - hi_b) packed.
+__device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  hi = pk_bf16(a, b);
+  lo = pk_bf16(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
 
 // hi = bf16(v), lo = bf16(v - hi), packed 8 -> uint4 each.
 __device__ __forceinline__ void split8(const float (&v)[8], uint4& hi,
@@ -805,14 +819,11 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
         // lane holds A[16 rw + 4 g + i][16 jb + n]: half of an A record
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-          uint32_t h[4], l[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            h[i] = f2bf(acc[jb][i]);
-            l[i] = f2bf(acc[jb][i] - bf2f(h[i]));
-          }
-          ARH[rw >> 1][jb][lane][rw & 1] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-          ARL[rw >> 1][jb][lane][rw & 1] = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+          uint32_t h01, l01, h23, l23;
+          split2(acc[jb][0], acc[jb][1], h01, l01);
+          split2(acc[jb][2], acc[jb][3], h23, l23);
+          ARH[rw >> 1][jb][lane][rw & 1] = make_uint2(h01, h23);
+          ARL[rw >> 1][jb][lane][rw & 1] = make_uint2(l01, l23);
         }
       }
       __syncthreads();
@@ -983,10 +994,11 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
 
   // Direct loads of the chunk starting at global row r0 into buffer b:
   // wave w fetches records w LPW .. w LPW + LPW - 1, in NGRP groups issued
-  // at points spread over the matrix-core work of the previous chunk (a wave
-  // whose load cannot enter the memory pipeline stalls at the issue: one
-  // burst of all loads would hold every wave up at once, and a stall in a
-  // phase without matrix work would hold up the workgroup's barrier).
+  // while the chunk before it is processed: after the chunk's first barrier,
+  // early in part 1, at the end of part 1 and after the finalise (a wave
+  // whose load cannot enter the memory pipeline stalls at the issue, so one
+  // burst of all loads would hold every wave up at once; the last group
+  // still lands a whole part 2 before it is needed).
   constexpr int NGRP = (LPW % 4 == 0) ? 4 : ((LPW % 2 == 0) ? 2 : 1);
   constexpr int LPG = LPW / NGRP;  // loads per group
   const int voff_lane = (n * LDT + 8 * g) * 2;
@@ -1059,7 +1071,8 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
             if constexpr (X2) acc[f][m] = mfma_bf16(xb, sh[f][j], acc[f][m]);
           }
         }
-        if (NGRP > 1 && has_next && j == SPW / 2) issue(nr0, buf ^ 1, 1);
+        if (NGRP > 1 && has_next && j == SPW / 4) issue(nr0, buf ^ 1, 1);
+        if (NGRP > 2 && has_next && j == SPW - 1) issue(nr0, buf ^ 1, 2);
       }
 #pragma unroll
       for (int f = 0; f < FPW; ++f)
@@ -1085,21 +1098,42 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
           v[2] += __uint_as_float(u[p].z);
           v[3] += __uint_as_float(u[p].w);
         }
-        uint32_t h[4], l[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          h[i] = f2bf(v[i]);
-          l[i] = f2bf(v[i] - bf2f(h[i]));
-        }
+        uint32_t h01, l01, h23, l23;
+        split2(v[0], v[1], h01, l01);
+        split2(v[2], v[3], h23, l23);
         uint2* dst = (uint2*)&Pa[0][o][0];  // hi pairs, then lo pairs
-        dst[lane] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-        dst[64 + lane] = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+        dst[lane] = make_uint2(h01, h23);
+        dst[64 + lane] = make_uint2(l01, l23);
       }
     }
-    if (NGRP > 2 && has_next) issue(nr0, buf ^ 1, 2);
-    __syncthreads();
+    if (NGRP > 3 && has_next) issue(nr0, buf ^ 1, 3);
     // ---- part 2: Z[:, 64 w + 16 q + n] += A^T Xhat, Gram tiles
     {
+      const char* xb0 = (const char*)&Xs[buf][0][0];
+      // Xhat operands of 16-TR tile q by transposing reads
+      auto load_b = [&](int q, uint4& bh, uint4& bl) {
+        const int t = 64 * wave + 16 * q + 4 * tr_q;  // first of this lane's 4 TRs
+        const int st = t >> 5, gq = (t & 31) >> 3, half = (t & 7) >> 2;
+        const int in_rec = ((4 * g + tr_r) + 16 * gq) * 16 + 8 * half;
+        {
+          const v4s r1 = ds_tr16(xb0 + rec(0, 0, st) * 1024 + in_rec);
+          const v4s r2 = ds_tr16(xb0 + rec(0, 1, st) * 1024 + in_rec);
+          bh = pack_tr(r1, r2);
+        }
+        if constexpr (X2) {
+          const v4s r1 = ds_tr16(xb0 + rec(1, 0, st) * 1024 + in_rec);
+          const v4s r2 = ds_tr16(xb0 + rec(1, 1, st) * 1024 + in_rec);
+          bl = pack_tr(r1, r2);
+        }
+      };
+      // Tile 0's reads do not depend on the finalise, so they go out before
+      // the barrier that publishes it.  LDS operations of a wave complete in
+      // order: once at most those reads are outstanding, this wave's
+      // finalise writes are done, which is all the barrier has to wait for.
+      uint4 bh0, bl0;
+      asm volatile("" ::: "memory");
+      load_b(0, bh0, bl0);
+      asm volatile("s_waitcnt lgkmcnt(%0)\n\ts_barrier" :: "n"(X2 ? 4 : 2) : "memory");
       // A operands of block jb: the hi (lo) pairs of tiles 0 and 1 from the
       // two outputs' slots, 8 bytes per lane each, straight into the
       // operand's two register pairs
@@ -1112,30 +1146,16 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
         ah[jb] = make_uint4(h0.x, h0.y, h1.x, h1.y);
         al[jb] = make_uint4(l0.x, l0.y, l1.x, l1.y);
       }
-      const char* xb0 = (const char*)&Xs[buf][0][0];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int t = 64 * wave + 16 * q + 4 * tr_q;  // first of this lane's 4 TRs
-        const int st = t >> 5, gq = (t & 31) >> 3, half = (t & 7) >> 2;
-        const int in_rec = ((4 * g + tr_r) + 16 * gq) * 16 + 8 * half;
-        uint4 bh, bl;
-        {
-          const v4s r1 = ds_tr16(xb0 + rec(0, 0, st) * 1024 + in_rec);
-          const v4s r2 = ds_tr16(xb0 + rec(0, 1, st) * 1024 + in_rec);
-          bh = pack_tr(r1, r2);
-        }
-        if constexpr (X2) {
-          const v4s r1 = ds_tr16(xb0 + rec(1, 0, st) * 1024 + in_rec);
-          const v4s r2 = ds_tr16(xb0 + rec(1, 1, st) * 1024 + in_rec);
-          bl = pack_tr(r1, r2);
-        }
+        uint4 bh = bh0, bl = bl0;
+        if (q > 0) load_b(q, bh, bl);
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
           zacc[jb][q] = mfma_bf16(ah[jb], bh, zacc[jb][q]);
           zacc[jb][q] = mfma_bf16(al[jb], bh, zacc[jb][q]);
           if constexpr (X2) zacc[jb][q] = mfma_bf16(ah[jb], bl, zacc[jb][q]);
         }
-        if (q == 1 && NGRP > 3 && has_next) issue(nr0, buf ^ 1, 3);
       }
       int p = 0;
 #pragma unroll
