@@ -351,14 +351,15 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* rowc,
 }
 
 // ---------------------------------------------------------------------------
-// M-phase: A = Xhat S^T over all subjects' rows (one grouped launch).
-// Workgroup = 4 waves; each wave owns 64-row tiles (4 MFMA row blocks) and the
-// full K (= features, padded) width; TRs are the contraction.
+// M-phase, FP32 storage: A = Xhat S^T over all subjects' rows (one grouped
+// launch).  Workgroup = 4 waves; each wave owns 64-row tiles (4 MFMA row
+// blocks) and the full K (= features, padded) width; TRs are the contraction.
 // ---------------------------------------------------------------------------
 
 template <int KP, int PREC>
 __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
   if (a.sc->status) return;  // an earlier step of this iteration failed
+  static_assert(PREC == P_FP32, "the BF16 forms run k_mphase_s");
   constexpr int NB = KP / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
 
     // Operands of step tb + 1 are loaded while step tb's products run
     // (double buffer).
-    if constexpr (PREC == P_FP32) {
+    {
       const float* X = (const float*)a.xh + rowt * a.ldt;  // uniform
       const int ld = (int)a.ldt;
       const int nstep = ld / 16;
@@ -414,53 +415,6 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
         if (tb + 2 < nstep) load(tb + 2, 0);
         comp(1);
       }
-    } else {
-      const uint16_t* XH = (const uint16_t*)a.xh + rowt * a.ldt;  // uniform
-      const uint16_t* XL = (const uint16_t*)a.xl + rowt * a.ldt;
-      const int ld = (int)a.ldt;
-      const int nstep = ld / 32;
-      uint4 xh4[2][4], xl4[2][4], sh4[2][NB], sl4[2][NB];
-      auto load = [&](int tb, int b) __attribute__((always_inline)) {
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          const int o = (16 * mb + n) * ld + 32 * tb + 8 * g;
-          if (mb < 2 || h1) {
-            xh4[b][mb] = *(const uint4*)(XH + o);
-            if constexpr (PREC == P_BF16X2) xl4[b][mb] = *(const uint4*)(XL + o);
-          } else {
-            xh4[b][mb] = make_uint4(0, 0, 0, 0);
-            xl4[b][mb] = make_uint4(0, 0, 0, 0);
-          }
-        }
-        const uint4* SH = (const uint4*)a.sh + tb * NB * 64;
-        const uint4* SL = (const uint4*)a.sl + tb * NB * 64;
-#pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-          sh4[b][jb] = SH[jb * 64 + lane];
-          sl4[b][jb] = SL[jb * 64 + lane];
-        }
-      };
-      auto comp = [&](int b) __attribute__((always_inline)) {
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          if (mb >= 2 && !h1) continue;
-#pragma unroll
-          for (int jb = 0; jb < NB; ++jb) {
-            acc[mb][jb] = mfma_bf16(xh4[b][mb], sh4[b][jb], acc[mb][jb]);
-            acc[mb][jb] = mfma_bf16(xh4[b][mb], sl4[b][jb], acc[mb][jb]);
-            if constexpr (PREC == P_BF16X2)
-              acc[mb][jb] = mfma_bf16(xl4[b][mb], sh4[b][jb], acc[mb][jb]);
-          }
-        }
-      };
-      load(0, 0);
-      for (int tb = 0; tb < nstep; tb += 2) {
-        if (tb + 1 < nstep) load(tb + 1, 1);
-        comp(0);
-        if (tb + 1 >= nstep) break;
-        if (tb + 2 < nstep) load(tb + 2, 0);
-        comp(1);
-      }
     }
     // Accumulator lane l holds A[rowt + 16 mb + 4 g + i][16 jb + n]; two
     // stacked row blocks are exactly one A record.
@@ -474,16 +428,148 @@ __global__ __launch_bounds__(256) void k_mphase(MArgs a) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = acc[2 * h + (e >> 2)][jb][e & 3];
         const int64_t rec = (rb * NB + jb) * 64 + lane;
-        if constexpr (PREC == P_FP32) {
-          float4* AR = (float4*)a.ah;
-          AR[rec * 2] = make_float4(v[0], v[1], v[2], v[3]);
-          AR[rec * 2 + 1] = make_float4(v[4], v[5], v[6], v[7]);
+        float4* AR = (float4*)a.ah;
+        AR[rec * 2] = make_float4(v[0], v[1], v[2], v[3]);
+        AR[rec * 2 + 1] = make_float4(v[4], v[5], v[6], v[7]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M-phase, BF16 forms: A = Xhat S^T as k_mphase (a wave's tile is 64 rows,
+// a step 32 TRs), with the S operands of each step shared by the
+// workgroup's four waves through LDS (two slots, one barrier per step)
+// instead of each wave reading them from L2.  That quarters the S loads per
+// Xhat byte, which compete with the Xhat loads for the CU's memory pipeline,
+// and leaves a wave few enough registers (accumulators, double-buffered Xhat
+// operands, the S staging) for two workgroups to share a CU.  Every wave of
+// a workgroup runs the same rounds of tiles and steps (a wave without a tile
+// in the last round only helps stage S), so the barriers match.
+// ---------------------------------------------------------------------------
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(256, 2) void k_mphase_s(MArgs a) {
+  if (a.sc->status) return;  // an earlier step of this iteration failed
+  static_assert(PREC != P_FP32, "BF16 forms only");
+  constexpr bool X2 = PREC == P_BF16X2;
+  constexpr int NB = KP / 16;
+  constexpr int NS = 2 * NB * 64;            // S records of one step (uint4)
+  constexpr int NSU = (NS + 255) / 256;      // staged per thread
+  __shared__ uint4 Ss[2][NS];                // [slot][plane][block][lane]
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t tb0 = (int64_t)blockIdx.x * a.tiles_per_wg;
+  int64_t te = tb0 + a.tiles_per_wg;
+  if (te > a.ntiles) te = a.ntiles;
+  if (te <= tb0) return;  // whole workgroup
+  const int nround = (int)((te - tb0 + 3) / 4);
+  const int ld = (int)a.ldt;
+  const int nstep = ld / 32;
+  const uint4* SH = (const uint4*)a.sh;
+  const uint4* SL = (const uint4*)a.sl;
+
+  // S of step tb: records [tb][block][lane] of each plane, staged through
+  // registers (thread tid carries entries tid + 256 u) into a slot.
+  uint4 st[NSU];
+  auto s_load = [&](int tb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NSU; ++u) {
+      const int idx = tid + 256 * u;
+      st[u] = make_uint4(0, 0, 0, 0);
+      if (NS % 256 == 0 || idx < NS) {
+        const int pl = idx / (NB * 64), e = idx % (NB * 64);
+        st[u] = (pl ? SL : SH)[(int64_t)tb * NB * 64 + e];
+      }
+    }
+  };
+  auto s_store = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NSU; ++u) {
+      const int idx = tid + 256 * u;
+      if (NS % 256 == 0 || idx < NS) Ss[b][idx] = st[u];
+    }
+  };
+  s_load(0);
+  s_store(0);
+  __syncthreads();
+  int slot = 0;
+
+  for (int rd = 0; rd < nround; ++rd) {
+    const int64_t tile = tb0 + 4 * rd + wave;
+    const bool valid = tile < te;
+    const int64_t rowt = a.row_begin + (valid ? tile : tb0) * 64;
+    const bool h1 = valid && rowt + 32 < a.row_end;  // second 32-row half valid
+    f32x4 acc[4][NB];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) acc[mb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* XH = (const uint16_t*)a.xh + rowt * a.ldt;  // uniform
+    const uint16_t* XL = (const uint16_t*)a.xl + rowt * a.ldt;
+    uint4 xh4[2][4], xl4[2][4];
+    auto load_x = [&](int tb, int b) __attribute__((always_inline)) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const int o = (16 * mb + n) * ld + 32 * tb + 8 * g;
+        if (valid && (mb < 2 || h1)) {
+          xh4[b][mb] = *(const uint4*)(XH + o);
+          if constexpr (X2) xl4[b][mb] = *(const uint4*)(XL + o);
         } else {
-          uint4 hi, lo;
-          split8(v, hi, lo);
-          ((uint4*)a.ah)[rec] = hi;
-          ((uint4*)a.al)[rec] = lo;
+          xh4[b][mb] = make_uint4(0, 0, 0, 0);
+          if constexpr (X2) xl4[b][mb] = make_uint4(0, 0, 0, 0);
         }
+      }
+    };
+    // One step: stage the next step's S (after a round's last step, step 0
+    // again for the next round), load the next Xhat operands, the products
+    // of step tb with S from slot `slot`, then hand the next slot over at
+    // the barrier.
+    auto step = [&](int tb, int b) __attribute__((always_inline)) {
+      s_load(tb + 1 < nstep ? tb + 1 : 0);
+      if (tb + 1 < nstep) load_x(tb + 1, b ^ 1);
+      if (valid) {
+        const uint4* S0 = &Ss[slot][0];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          const uint4 sh = S0[jb * 64 + lane], sl = S0[(NB + jb) * 64 + lane];
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) {
+            if (mb >= 2 && !h1) continue;
+            acc[mb][jb] = mfma_bf16(xh4[b][mb], sh, acc[mb][jb]);
+            acc[mb][jb] = mfma_bf16(xh4[b][mb], sl, acc[mb][jb]);
+            if constexpr (X2) acc[mb][jb] = mfma_bf16(xl4[b][mb], sh, acc[mb][jb]);
+          }
+        }
+      }
+      s_store(slot ^ 1);
+      __syncthreads();
+      slot ^= 1;
+    };
+    load_x(0, 0);
+    for (int tb = 0; tb < nstep; tb += 2) {
+      step(tb, 0);
+      if (tb + 1 >= nstep) break;
+      step(tb + 1, 1);
+    }
+    if (!valid) continue;
+    // Accumulator lane l holds A[rowt + 16 mb + 4 g + i][16 jb + n]; two
+    // stacked row blocks are exactly one A record.
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !h1) break;
+      const int64_t rb = rowt / 32 + h;
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = acc[2 * h + (e >> 2)][jb][e & 3];
+        const int64_t rec = (rb * NB + jb) * 64 + lane;
+        uint4 hi, lo;
+        split8(v, hi, lo);
+        ((uint4*)a.ah)[rec] = hi;
+        ((uint4*)a.al)[rec] = lo;
       }
     }
   }
@@ -2455,7 +2541,10 @@ hipError_t launch_rowsum(hipStream_t st, int N, const double* rowc,
 hipError_t launch_mphase(hipStream_t st, int kp, int prec, int grid,
                          const MArgs& a) {
   SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
-      hipLaunchKernelGGL((k_mphase<KP, PR>), dim3(grid), dim3(256), 0, st, a)));
+      if constexpr (PR == P_FP32)
+        hipLaunchKernelGGL((k_mphase<KP, PR>), dim3(grid), dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_mphase_s<KP, PR>), dim3(grid), dim3(256), 0, st, a)));
   return hipGetLastError();
 }
 hipError_t launch_ephase(hipStream_t st, int kp, int prec, int grid,
@@ -2637,7 +2726,10 @@ hipError_t launch_map(hipStream_t st, int kp, const MapArgs& a) {
 
 hipError_t occupancy_mphase(int kp, int prec, int* blocks) {
   SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_mphase<KP, PR>, 256, 0)));
+      if constexpr (PR == P_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_mphase<KP, PR>, 256, 0);
+      else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_mphase_s<KP, PR>, 256, 0)));
   return hipErrorInvalidValue;
 }
 hipError_t occupancy_ephase(int kp, int prec, int* blocks) {

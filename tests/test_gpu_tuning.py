@@ -1,6 +1,6 @@
 """Launch shapes (srm_tuning): every candidate the autotuner can pick reaches
 the oracle's EM iterate within the bar, on the one-pass sweep (register-ring
-and LDS-staged kernels, both BF16 forms, K paddings 16, 32, 64), the two-pass
+and LDS-staged kernels, both BF16 forms, K paddings 16, 32, 48, 64), the two-pass
 sweep and the sample-space iteration; srm_autotune leaves the carried state
 unchanged and keeps a candidate; SRM_AUTOTUNE reads and writes the cache."""
 import os
@@ -43,6 +43,14 @@ CASES = {
                               sigma_hi=2.0),
     # K padding 16 with two waves (t = 70), ragged subjects
     "ragged": synth.Workload("ragged", 5, 33, 250, 70, 7, 6),
+    # K padding 48 (three feature blocks: one feature group, every wave its
+    # own TR part) with six waves (t = 300)
+    "k40t300": synth.Workload("k40t300", 3, 400, 1900, 300, 40, 4, sigma_lo=0.5,
+                              sigma_hi=2.0),
+    # K padding 48 with eight waves (t = 500): the staged kernel's LDS would
+    # exceed 160 KB, so only the register-ring kernel runs one-pass
+    "k40t500": synth.Workload("k40t500", 3, 400, 1900, 500, 40, 4, sigma_lo=0.5,
+                              sigma_hi=2.0),
     # two-pass sweep (FP32 storage), many ranges and slices
     "slices": synth.Workload("slices", 6, 3000, 9000, 300, 20, 4, sigma_lo=0.5, sigma_hi=2.0),
 }
@@ -55,10 +63,18 @@ def _oracle(d, w, prec):
     return oracle.em_fit(d["X"], w.k, w.n_iter, d["W0"], final_loglik=True)
 
 
+# one-pass sweep kernels each case's candidates must include (0 register
+# ring, 1 staged)
+KERNELS = {"wide2": [0, 1], "k20": [0, 1], "k50t200": [0, 1], "ragged": [0, 1],
+           "k40t300": [0, 1], "k40t500": [0]}
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("case,prec,gram", [
     ("wide2", "bf16x2", False), ("wide2", "bf16", False), ("k20", "bf16x2", False),
-    ("k50t200", "bf16x2", False), ("ragged", "bf16", False), ("slices", "fp32", False), ("slices", "bf16x2", True)])
+    ("k50t200", "bf16x2", False), ("ragged", "bf16", False), ("k40t300", "bf16x2", False),
+    ("k40t500", "bf16x2", False), ("k40t300", "bf16", False), ("slices", "fp32", False),
+    ("slices", "bf16x2", True)])
 def test_every_candidate_meets_the_bar(case, prec, gram):
     srm = _srm()
     w = CASES[case]
@@ -71,7 +87,7 @@ def test_every_candidate_meets_the_bar(case, prec, gram):
     kernels = sorted({c["sweep_kernel"] for c in cands})
     _say(f"[case] {case}/{prec} sweep={sweep}: {len(cands)} candidates, kernels {kernels}")
     if sweep == "one_pass":
-        assert kernels == [0, 1], "the staged kernel applies to these shapes"
+        assert kernels == KERNELS[case], kernels
     worst = {}
     for t in cands:
         g = srm.SRM(d["X"], w.k, prec=prec, W0=d["W0"], gram=gram)
