@@ -30,6 +30,7 @@ hipError_t launch_mphase(hipStream_t, int, int, int, const MArgs&);
 hipError_t launch_ephase(hipStream_t, int, int, int, const EArgs&);
 hipError_t launch_ereduce(hipStream_t, int, int, int, const RArgs&);
 int ereduce_ct(int kp);
+int ephase_panel(int prec);  // TRs per E-phase workgroup
 hipError_t launch_post_prep(hipStream_t, int, const PrepArgs&);
 hipError_t launch_post_s(hipStream_t, int, int, int, const SArgs&);
 hipError_t launch_post_fin(hipStream_t, int, const FinArgs&);
@@ -276,8 +277,9 @@ srm_status make_plan(const srm_desc* d, Plan& p) {
     row += p.subj[i].vp;
   }
   p.total_rows = row;
-  // E-phase: equal row ranges (multiples of 32 rows) split at subject ends.
-  p.npanel = (int)((p.ldt + 255) / 256);
+  // E-phase: equal row ranges (multiples of 32 rows) split at subject ends,
+  // each swept by npanel workgroups side by side in TRs.
+  p.npanel = (int)((p.ldt + ephase_panel(p.prec) - 1) / ephase_panel(p.prec));
   p.fused = fused_supported(p.KP, p.prec, p.ldt) && !(d->flags & (SRM_TWO_PASS | SRM_GRAM));
   p.rct = ereduce_ct(p.KP);
   p.ncol_r = (int)(p.ldt / p.rct);

@@ -576,9 +576,10 @@ __global__ __launch_bounds__(256, 2) void k_mphase_s(MArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// E-phase: per slice s (rows of one subject), Z_s = A_s^T Xhat_s (KP x ldt)
-// and, for the M-step, G_s = A_s^T A_s (upper 16x16 tiles).  Workgroup =
-// 4 waves, each wave a 64-TR column panel; rows are the contraction.
+// E-phase, FP32 storage: per slice s (rows of one subject),
+// Z_s = A_s^T Xhat_s (KP x ldt) and, for the M-step, G_s = A_s^T A_s (upper
+// 16x16 tiles).  Workgroup = 4 waves, each wave a 64-TR column panel; rows
+// are the contraction.
 // Workgroup w owns an equal share of all rows (split at subject boundaries
 // into slices); the npanel column panels of a row range sit on one XCD.
 // ---------------------------------------------------------------------------
@@ -586,6 +587,7 @@ __global__ __launch_bounds__(256, 2) void k_mphase_s(MArgs a) {
 template <int KP, int PREC>
 __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
   if (a.sc->status) return;
+  static_assert(PREC == P_FP32, "the BF16 forms run k_ephase_s");
   constexpr int NB = KP / 16;
   constexpr int NPAIR = NB * (NB + 1) / 2;
   constexpr int NG = (NPAIR + 3) / 4;
@@ -611,11 +613,10 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
     for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // Operands of the next step are loaded while the current step's
-    // products run (double buffer).  FP32 steps are 16-row halves of the
-    // 32-row A records; BF16 steps are whole records (the K = 32 products
-    // consume all 32 rows at once).
+    // products run (double buffer).  Steps are 16-row halves of the 32-row
+    // A records.
     const int ld = (int)a.ldt;
-    if constexpr (PREC == P_FP32) {
+    {
       const int nstep = sl.nrows / 16;
       float4 av[2][NB], xv[2][4];
       auto load = [&](int hs, int b) __attribute__((always_inline)) {
@@ -665,94 +666,6 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
         if (hs + 2 < nstep) load(hs + 2, 0);
         comp(1);
       }
-    } else {
-      const int nblk = sl.nrows / 32;
-      // Above KP = 80 with both halves of X, a second A buffer would spill:
-      // there A is loaded at the start of its step (L2-resident, shared by
-      // the workgroup's four waves) and only X is double-buffered.
-      constexpr int DA = (PREC == P_BF16X2 && KP > 80) ? 1 : 2;
-      uint4 ah[DA][NB], al[DA][NB];
-      uint2 xv[2][8], xw[2][8];
-      auto load_a = [&](int blk, int b) __attribute__((always_inline)) {
-        const int64_t rb = (sl.row0 + 32 * blk) / 32;
-        const uint4* AH = (const uint4*)a.ah + rb * NB * 64;  // uniform
-        const uint4* AL = (const uint4*)a.al + rb * NB * 64;
-#pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-          ah[b][jb] = AH[jb * 64 + lane];
-          al[b][jb] = AL[jb * 64 + lane];
-        }
-      };
-      auto load = [&](int blk, int b) __attribute__((always_inline)) {
-        const int64_t row0 = sl.row0 + 32 * blk;
-        if constexpr (DA == 2) load_a(blk, b);
-        if (do_z) {
-          const int64_t xbase = row0 * a.ldt + cbase;  // wave-uniform
-          const uint16_t* XH = (const uint16_t*)a.xh + xbase;
-          const uint16_t* XL = (const uint16_t*)a.xl + xbase;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int o = (4 * g + (e & 3) + 16 * (e >> 2)) * ld + 4 * n;
-            xv[b][e] = *(const uint2*)(XH + o);
-            if constexpr (PREC == P_BF16X2) xw[b][e] = *(const uint2*)(XL + o);
-          }
-        }
-      };
-      auto comp = [&](int blk, int b) __attribute__((always_inline)) {
-        const int ba = DA == 2 ? b : 0;
-        if constexpr (DA == 1) load_a(blk, 0);
-        if (do_z) {
-          // In-register 8x4 transpose: operand q holds column 4n+q of the
-          // 8 rows, two rows per dword.
-          uint4 bh[4], bl[4];
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const uint2 u0 = xv[b][2 * d], u1 = xv[b][2 * d + 1];
-            ((uint32_t*)&bh[0])[d] = (u0.x & 0xffffu) | (u1.x << 16);
-            ((uint32_t*)&bh[1])[d] = (u0.x >> 16) | (u1.x & 0xffff0000u);
-            ((uint32_t*)&bh[2])[d] = (u0.y & 0xffffu) | (u1.y << 16);
-            ((uint32_t*)&bh[3])[d] = (u0.y >> 16) | (u1.y & 0xffff0000u);
-            if constexpr (PREC == P_BF16X2) {
-              const uint2 w0 = xw[b][2 * d], w1 = xw[b][2 * d + 1];
-              ((uint32_t*)&bl[0])[d] = (w0.x & 0xffffu) | (w1.x << 16);
-              ((uint32_t*)&bl[1])[d] = (w0.x >> 16) | (w1.x & 0xffff0000u);
-              ((uint32_t*)&bl[2])[d] = (w0.y & 0xffffu) | (w1.y << 16);
-              ((uint32_t*)&bl[3])[d] = (w0.y >> 16) | (w1.y & 0xffff0000u);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-              acc[jb][q] = mfma_bf16(ah[ba][jb], bh[q], acc[jb][q]);
-              acc[jb][q] = mfma_bf16(al[ba][jb], bh[q], acc[jb][q]);
-              if constexpr (PREC == P_BF16X2)
-                acc[jb][q] = mfma_bf16(ah[ba][jb], bl[q], acc[jb][q]);
-            }
-        }
-        if (do_g) {
-          int p = 0;
-#pragma unroll
-          for (int j1 = 0; j1 < NB; ++j1)
-#pragma unroll
-            for (int j2 = j1; j2 < NB; ++j2, ++p)
-              if ((p & 3) == wave) {
-                gacc[p >> 2] = mfma_bf16(ah[ba][j1], ah[ba][j2], gacc[p >> 2]);
-                gacc[p >> 2] = mfma_bf16(ah[ba][j1], al[ba][j2], gacc[p >> 2]);
-                gacc[p >> 2] = mfma_bf16(al[ba][j1], ah[ba][j2], gacc[p >> 2]);
-                // lo*lo too: its error would scale with cond(A^T A) in W^T W.
-                gacc[p >> 2] = mfma_bf16(al[ba][j1], al[ba][j2], gacc[p >> 2]);
-              }
-        }
-      };
-      if (nblk > 0) load(0, 0);
-      for (int blk = 0; blk < nblk; blk += 2) {
-        if (blk + 1 < nblk) load(blk + 1, 1);
-        comp(blk, 0);
-        if (blk + 1 >= nblk) break;
-        if (blk + 2 < nblk) load(blk + 2, 0);
-        comp(blk + 1, 1);
-      }
     }
     // Z tile: lane holds Z[16 jb + 4 g + i][cbase + 4 n + q].
     if (do_z) {
@@ -782,6 +695,207 @@ __global__ __launch_bounds__(256) void k_ephase(EArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// E-phase, BF16 forms: Z_s = A_s^T Xhat_s and G_s = A_s^T A_s as k_ephase,
+// with both operands staged in LDS by direct loads one 32-row block ahead
+// (double buffer): the block of Xhat (32 rows x the workgroup's 512-TR
+// panel, records as in k_staged) and the block's A records, which the eight
+// waves share instead of each reading them from L2.  The rows-as-K operand
+// of Xhat comes from transposing LDS reads, so a wave holds no Xhat in
+// registers and two waves fit a SIMD.  Wave w adds TRs 64 w .. 64 w + 63 of
+// the panel and its share of the Gram tiles (panel 0).  One barrier per
+// block: after it the block's loads have landed for every wave, and every
+// wave is done with the buffer the next loads refill.
+// ---------------------------------------------------------------------------
+
+constexpr int kEphasePanel = 512;  // TRs per k_ephase_s workgroup
+
+template <int KP, int PREC>
+__global__ __launch_bounds__(512) void k_ephase_s(EArgs a) {
+  if (a.sc->status) return;  // an earlier step of this iteration failed
+  static_assert(PREC != P_FP32, "BF16 forms only");
+  constexpr bool X2 = PREC == P_BF16X2;
+  constexpr int PL = X2 ? 2 : 1;
+  constexpr int NW = 8;
+  constexpr int NB = KP / 16;
+  constexpr int NSTEP = kEphasePanel / 32;   // 32-TR steps of a panel
+  constexpr int NREC = PL * 2 * NSTEP;       // Xhat records per block
+  constexpr int LPW = NREC / NW;             // Xhat loads per wave per block
+  constexpr int NGRP = 4, LPG = LPW / NGRP;
+  static_assert(LPW % NGRP == 0, "");
+  constexpr int NAR = 2 * NB;                // A records per block (hi, lo)
+  constexpr int NPAIR = NB * (NB + 1) / 2;
+  constexpr int NG = (NPAIR + NW - 1) / NW;
+  __shared__ uint4 Xs[2][NREC][64];
+  __shared__ uint4 As[2][NAR][64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int range = w / a.npanel, panel = w % a.npanel;
+  const int64_t ldt = a.ldt;
+  const int64_t c0 = (int64_t)panel * kEphasePanel;   // first TR of the panel
+  const int64_t nin = (ldt - c0) / 32;
+  const int nst = nin < NSTEP ? (int)nin : NSTEP;  // steps inside ldt
+  const bool do_z = 64 * wave < 32 * nst;
+  const bool do_g = a.want_gram && panel == 0;
+  const int sb = a.range_slice[range], se = a.range_slice[range + 1];
+  if (sb >= se) return;  // whole workgroup
+  const uint16_t* XH = (const uint16_t*)a.xh;
+  const uint16_t* XL = (const uint16_t*)a.xl;
+  const uint4* AH = (const uint4*)a.ah;
+  const uint4* AL = (const uint4*)a.al;
+
+  // Loads of the block at global row r0 into buffer b: Xhat records r =
+  // w LPW .. w LPW + LPW - 1 in NGRP groups (records of steps beyond ldt are
+  // not loaded; only waves without TRs there would read them), A records
+  // w, w + NW, ... with group 0.
+  const int voff_lane = (int)((n * ldt + 8 * g) * 2);
+  auto issue = [&](int64_t r0, int b, int grp) __attribute__((always_inline)) {
+    const uint32_t xbytes = (uint32_t)((32 * ldt - c0) * 2);
+    const v4i_rsrc RH = make_rsrc_v4(XH + r0 * ldt + c0, xbytes);
+    const v4i_rsrc RL = make_rsrc_v4(XL + r0 * ldt + c0, xbytes);
+#pragma unroll
+    for (int jj = 0; jj < LPG; ++jj) {
+      const int r = wave * LPW + grp * LPG + jj;
+      const int pl = r / (2 * NSTEP), rb = (r / NSTEP) & 1, st = r % NSTEP;
+      if (st < nst)
+        load_lds16(pl ? RL : RH, &Xs[b][r][0], voff_lane, (int)((16 * rb * ldt + 32 * st) * 2));
+    }
+    if (grp == 0) {
+      const int64_t rb = r0 / 32;
+      const v4i_rsrc QH = make_rsrc_v4(AH + rb * NB * 64, NB * 1024);
+      const v4i_rsrc QL = make_rsrc_v4(AL + rb * NB * 64, NB * 1024);
+#pragma unroll
+      for (int r = wave; r < NAR; r += NW)
+        load_lds16(r < NB ? QH : QL, &As[b][r][0], lane * 16, (r % NB) * 1024);
+    }
+  };
+  auto rec = [](int pl, int rb, int st) { return (pl * 2 + rb) * NSTEP + st; };
+
+  f32x4 zacc[NB][4];
+  f32x4 gacc[NG];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zacc[jb][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < NG; ++p) gacc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int s = sb, cr = 0, buf = 0;
+  int64_t row0;
+  int32_t nrows;
+  slice_s(a.slices + s, row0, nrows);
+#pragma unroll
+  for (int grp = 0; grp < NGRP; ++grp) issue(row0, 0, grp);
+  // Transposing reads: lane 4r + q of group g reads TRs 4q..4q+3 of rows
+  // 4g + r (first read) and 16 + 4g + r (second read) of a 16-TR tile.
+  const int tr_r = (lane & 15) >> 2, tr_q = lane & 3;
+  for (;;) {
+    int ns = s, ncr = cr + 32;
+    if (ncr >= nrows) { ns = s + 1; ncr = 0; }
+    const bool has_next = ns < se;
+    int64_t nrow0 = row0;
+    int32_t nnrows = nrows;
+    if (has_next && ns != s) slice_s(a.slices + ns, nrow0, nnrows);
+    const int64_t nr0 = nrow0 + ncr;  // the next block's first row
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+    __syncthreads();
+    if (has_next) issue(nr0, buf ^ 1, 0);
+    if (do_z) {
+      // Xhat operands of the wave's four 16-TR tiles, then the products
+      // block by block of features (A operands: record jb (hi) and NB + jb
+      // (lo), in lane order)
+      const char* xb0 = (const char*)&Xs[buf][0][0];
+      uint4 bh[4], bl[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = 64 * wave + 16 * q + 4 * tr_q;  // first of this lane's 4 TRs
+        const int st = t >> 5, gq = (t & 31) >> 3, half = (t & 7) >> 2;
+        const int in_rec = ((4 * g + tr_r) + 16 * gq) * 16 + 8 * half;
+        bh[q] = pack_tr(ds_tr16(xb0 + rec(0, 0, st) * 1024 + in_rec),
+                        ds_tr16(xb0 + rec(0, 1, st) * 1024 + in_rec));
+        if constexpr (X2)
+          bl[q] = pack_tr(ds_tr16(xb0 + rec(1, 0, st) * 1024 + in_rec),
+                          ds_tr16(xb0 + rec(1, 1, st) * 1024 + in_rec));
+      }
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        const uint4 ah = As[buf][jb][lane], al = As[buf][NB + jb][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          zacc[jb][q] = mfma_bf16(ah, bh[q], zacc[jb][q]);
+          zacc[jb][q] = mfma_bf16(al, bh[q], zacc[jb][q]);
+          if constexpr (X2) zacc[jb][q] = mfma_bf16(ah, bl[q], zacc[jb][q]);
+        }
+#pragma unroll
+        for (int grp = 1; grp < NGRP; ++grp)
+          if (jb == (grp * NB) / NGRP && has_next) issue(nr0, buf ^ 1, grp);
+        // keeps the scheduler from reading every block's A ahead (registers)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else if (has_next) {
+#pragma unroll
+      for (int grp = 1; grp < NGRP; ++grp) issue(nr0, buf ^ 1, grp);
+    }
+    if (do_g) {
+      int p = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NB; ++j2, ++p)
+          if ((p % NW) == wave) {
+            const uint4 h1 = As[buf][j1][lane], l1 = As[buf][NB + j1][lane];
+            const uint4 h2 = As[buf][j2][lane], l2 = As[buf][NB + j2][lane];
+            gacc[p / NW] = mfma_bf16(h1, h2, gacc[p / NW]);
+            gacc[p / NW] = mfma_bf16(h1, l2, gacc[p / NW]);
+            gacc[p / NW] = mfma_bf16(l1, h2, gacc[p / NW]);
+            // lo*lo too: its error would scale with cond(A^T A) in W^T W.
+            gacc[p / NW] = mfma_bf16(l1, l2, gacc[p / NW]);
+          }
+    }
+    if (ns != s || !has_next) {
+      // the slice is complete: lane holds Z[16 jb + 4 g + i][c0 + 64 w + 16 q + n]
+      if (do_z) {
+        // one feature row at a time (its offset is wave-uniform), so that
+        // the compiler does not keep every element's address live in the loop
+        float* zp = a.zpart + (int64_t)s * KP * ldt + c0 + 64 * wave + n + 4 * g * ldt;
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float* zr = zp + (int64_t)__builtin_amdgcn_readfirstlane((16 * jb + i) * (int)ldt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              zr[16 * q] = zacc[jb][q][i];
+              zacc[jb][q][i] = 0.f;
+            }
+          }
+      }
+      if (do_g) {
+        float* gp = a.gpart + (int64_t)s * KP * KP;
+        int p = 0;
+#pragma unroll
+        for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+          for (int j2 = j1; j2 < NB; ++j2, ++p)
+            if ((p % NW) == wave)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                gp[(16 * j1 + 4 * g + i) * KP + 16 * j2 + n] = gacc[p / NW][i];
+                gacc[p / NW][i] = 0.f;
+              }
+      }
+    }
+    if (!has_next) break;
+    s = ns;
+    cr = ncr;
+    row0 = nrow0;
+    nrows = nnrows;
+    buf ^= 1;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // One-pass sweep (BF16 forms, K padding <= 64, ldt in {128, 256, 384, 512}):
@@ -2550,9 +2664,13 @@ hipError_t launch_mphase(hipStream_t st, int kp, int prec, int grid,
 hipError_t launch_ephase(hipStream_t st, int kp, int prec, int grid,
                          const EArgs& a) {
   SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
-      hipLaunchKernelGGL((k_ephase<KP, PR>), dim3(grid), dim3(256), 0, st, a)));
+      if constexpr (PR == P_FP32)
+        hipLaunchKernelGGL((k_ephase<KP, PR>), dim3(grid), dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_ephase_s<KP, PR>), dim3(grid), dim3(512), 0, st, a)));
   return hipGetLastError();
 }
+int ephase_panel(int prec) { return prec == P_FP32 ? 256 : kEphasePanel; }
 int ereduce_ct(int kp) { return kp <= 64 ? 64 : (kp <= 96 ? 32 : 16); }
 hipError_t launch_ereduce(hipStream_t st, int kp, int ncol, int ngrp,
                           const RArgs& a) {
@@ -2734,7 +2852,10 @@ hipError_t occupancy_mphase(int kp, int prec, int* blocks) {
 }
 hipError_t occupancy_ephase(int kp, int prec, int* blocks) {
   SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase<KP, PR>, 256, 0)));
+      if constexpr (PR == P_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase<KP, PR>, 256, 0);
+      else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase_s<KP, PR>, 512, 0)));
   return hipErrorInvalidValue;
 }
 
