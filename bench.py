@@ -186,17 +186,24 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
     log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
     if warmup:
         g.fit(warmup)
+    compare = tune and tuning["chosen"] != default_shape
+    st_w = g.get_state() if compare else None
     log(f"[bench] timing {steps} iterations ({prec})")
     dt, ll = time_fit(g, steps)
     log(f"[bench] {prec}: {steps / dt:.2f} iters/s; profiling {prof_steps} iterations")
-    if tune and tuning["chosen"] != default_shape:
-        # the default shape on the same state, for comparison
+    if compare:
+        # the default shape over the same iterations from the same state (the
+        # first iterations of a fit can carry cold polar solves), for
+        # comparison; then the tuned fit's state again
+        st_t = g.get_state()
         cur = g.tuning()
         g.set_tuning(default_shape)
-        g.fit(1)
+        g.fit(1)  # captures the default shape's graph
+        g.set_state(st_w)
         dt_d, _ = time_fit(g, steps)
         tuning["default_ms_per_step"] = 1e3 * dt_d / steps
         g.set_tuning(cur)
+        g.set_state(st_t)
         log(f"[bench] default shape: {steps / dt_d:.2f} iters/s")
     info = g.info()  # after the timed srm_fit: which sweep ran, and whether it
     # replayed the captured graph

@@ -351,12 +351,16 @@ srm_status srm_get_info(const srm_ctx *ctx, srm_info *info);
  * srm_tuning_candidates: all candidates for this problem (out may be NULL to
  *                 query *count; at most capacity are written).
  * srm_autotune:   times candidates (one warm-up and `trials` iterations each,
- *                 direct launches, HIP events) by coordinate search (the sweep's
- *                 shapes, then the reduction's), restores the carried state
- *                 after every trial, puts the fastest in place, appends it to
- *                 the cache and returns it (best, best_ms per iteration, both
- *                 nullable).  A numeric failure in a trial returns its status
- *                 with the state and shapes unchanged. */
+ *                 direct launches, HIP events around the phases the shapes
+ *                 change: the sweep kernels and the E-step reduction, not the
+ *                 polar and posterior steps) by coordinate search (the sweep's
+ *                 shapes, then the reduction's), starting from the shapes in
+ *                 use, which a candidate replaces only when it is more than 1%
+ *                 faster; restores the carried state after every trial, puts
+ *                 the fastest in place, appends it to the cache and returns it
+ *                 (best, and best_ms, those phases' milliseconds per
+ *                 iteration; both nullable).  A numeric failure in a trial
+ *                 returns its status with the state and shapes unchanged. */
 enum { SRM_KERNEL_RING = 0, SRM_KERNEL_STAGED = 1 };
 typedef struct {
   int32_t sweep_kernel;

@@ -768,18 +768,35 @@ srm_status check_ready(const srm_ctx* c) {
 // `trials` timed ones (direct launches, HIP events on the context's stream),
 // after which the carried state is put back as it was.  *bad receives the
 // status an iteration raised (0: none).
-srm_status time_tuning(srm_ctx* c, const srm_tuning& t, int trials, hipEvent_t e0,
-                       hipEvent_t e1, double* ms, int* bad) {
+// Times `trials` iterations of shape t after one warm-up: the phases the
+// shapes change (M-phase, E-phase, one-pass sweep, sample-space products,
+// E-step reduction), each bracketed by HIP events as in srm_profile; the polar
+// and posterior steps are left out, since their time does not depend on the
+// shapes and varies from one iteration to the next (cold and warm polar
+// solves).
+srm_status time_tuning(srm_ctx* c, const srm_tuning& t, int trials, double* ms, int* bad) {
   srm_status st = apply_tuning(c, t);
   if (st != SRM_OK) return st;
+  for (int i = 0; i < 2 * SRM_NPHASE; ++i)
+    if (!c->ev[i]) HIP_OR_FAIL(hipEventCreate(&c->ev[i]));
   HIP_OR_FAIL(enqueue_iteration(c));
-  HIP_OR_FAIL(hipEventRecord(e0, c->stream));
-  for (int i = 0; i < trials; ++i) HIP_OR_FAIL(enqueue_iteration(c));
-  HIP_OR_FAIL(hipEventRecord(e1, c->stream));
-  HIP_OR_FAIL(hipEventSynchronize(e1));
-  float f = 0.f;
-  HIP_OR_FAIL(hipEventElapsedTime(&f, e0, e1));
-  *ms = (double)f / trials;
+  double sum = 0.0;
+  for (int i = 0; i < trials; ++i) {
+    for (auto& r : c->recorded) r = false;
+    c->profiling = true;
+    const hipError_t e = enqueue_iteration(c);
+    c->profiling = false;
+    HIP_OR_FAIL(e);
+    HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+    for (int ph : {SRM_PHASE_MPHASE, SRM_PHASE_EPHASE, SRM_PHASE_FUSED, SRM_PHASE_GRAM,
+                   SRM_PHASE_EREDUCE}) {
+      if (!c->recorded[ph]) continue;
+      float f = 0.f;
+      HIP_OR_FAIL(hipEventElapsedTime(&f, c->ev[2 * ph], c->ev[2 * ph + 1]));
+      sum += f;
+    }
+  }
+  *ms = sum / trials;
   Scalars sc{};
   HIP_OR_FAIL(hipMemcpyAsync(&sc, c->ws + c->p.o_sc, sizeof sc, hipMemcpyDeviceToHost,
                              c->stream));
@@ -1559,31 +1576,32 @@ srm_status srm_autotune(srm_ctx* c, int32_t trials, srm_tuning* best, double* be
   if (trials < 1) return fail(SRM_E_ARG, "trials must be >= 1");
   const srm_tuning start = c->tune;
   const int it0 = c->iters;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_OR_FAIL(hipEventCreate(&e0));
-  HIP_OR_FAIL(hipEventCreate(&e1));
   HIP_OR_FAIL(copy_state_regions(c, true));
   const auto all = tuning_candidates(c->p);
   // Coordinate search: the sweep's shapes at the default reduction, then the
-  // reduction's shapes at the best sweep.
+  // reduction's shapes at the best sweep.  The current shape is timed first
+  // and a candidate replaces the best only when it is faster by more than
+  // kTuneMargin, about the spread of repeated trials of one shape.
+  constexpr double kTuneMargin = 0.01;
   srm_tuning bt = start;
   double bms = 1e300;
   int bad = 0;
   auto trial = [&](const srm_tuning& t) -> srm_status {
     double ms = 0.0;
-    const srm_status st = time_tuning(c, t, trials, e0, e1, &ms, &bad);
+    const srm_status st = time_tuning(c, t, trials, &ms, &bad);
     if (st != SRM_OK || bad) return st;
-    if (ms < bms) {
+    if (ms < bms * (1.0 - kTuneMargin)) {
       bms = ms;
       bt = t;
     }
     return SRM_OK;
   };
   const int r0 = default_tuning(c->p).reduce_wgs;
+  s = trial(start);
   for (const auto& t : all) {
-    if (t.reduce_wgs != r0) continue;
-    s = trial(t);
     if (s != SRM_OK || bad) break;
+    if (t.reduce_wgs != r0 || same_tuning(t, start)) continue;
+    s = trial(t);
   }
   if (s == SRM_OK && !bad) {
     const srm_tuning sw = bt;
@@ -1595,8 +1613,6 @@ srm_status srm_autotune(srm_ctx* c, int32_t trials, srm_tuning* best, double* be
       if (s != SRM_OK || bad) break;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->iters = it0;
   c->a_valid = false;  // the trials overwrote the A records
   if (s != SRM_OK || bad) {
