@@ -388,7 +388,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     shape = head["tuning"].get("chosen", head["tuning"]["default"])
-    kname = "k_staged" if dom == "fused" and shape["sweep_kernel"] == 1 else f"k_{dom}"
+    if dom == "fused":
+        kname = "k_staged" if shape["sweep_kernel"] == 1 else "k_fused"
+    else:  # the two-pass kernels of the BF16 forms stage their shared operand in LDS
+        kname = f"k_{dom}" if hp == "fp32" else f"k_{dom}_s"
     roof["traffic"] = committed_traffic(kname, w.name if not args.subjects else
                                         f"{w.name}-{args.subjects}", hp)
     roof["kernel"] = kname
