@@ -47,7 +47,6 @@ bool fused_chunk_ok(int64_t ldt, int chunk);
 hipError_t launch_fused(hipStream_t, int, int, int64_t, int, int, const FusedArgs&);
 bool staged_supported(int kp, int prec, int64_t ldt);
 hipError_t launch_staged(hipStream_t, int, int, int64_t, int, const FusedArgs&);
-hipError_t occupancy_ephase(int, int, int*);
 size_t static_scratch_bytes();
 hipError_t static_scratch_setup(int dev);
 void* static_scratch_ptr(int dev);

@@ -2850,14 +2850,6 @@ hipError_t occupancy_mphase(int kp, int prec, int* blocks) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_mphase_s<KP, PR>, 256, 0)));
   return hipErrorInvalidValue;
 }
-hipError_t occupancy_ephase(int kp, int prec, int* blocks) {
-  SRM_KP_SWITCH(kp, SRM_PREC_SWITCH(prec,
-      if constexpr (PR == P_FP32)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase<KP, PR>, 256, 0);
-      else
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_ephase_s<KP, PR>, 512, 0)));
-  return hipErrorInvalidValue;
-}
 
 // ---------------------------------------------------------------------------
 // Static scratch of the no-allocation transform (srm_transform_static): the
