@@ -1142,10 +1142,10 @@ __global__ __launch_bounds__(NW * 64) void k_fused(FusedArgs a) {
 // matrix-core operand order (lane n + 16 g holds row n, TRs 8g..8g+7), which
 // is also the order a direct load deposits (lane j's 16 bytes at 16 j).
 // Partial sums: one 1 KB slot per (TR part, output), an output being a
-// (feature block, row tile) pair; the wave that finalises an output reads its
-// TR parts' slots and writes the output's half of the A record into the slot
-// of TR part 0, which no other wave reads: the 64 lanes' hi pairs, then their
-// lo pairs.
+// (feature block, row tile) pair.  An output is finalised by one of the waves
+// that formed a partial sum of it, which keeps that partial in registers and
+// reads the other TR parts' slots; the slots so left unused hold the A
+// operand records (hi and lo) of each feature block.
 // ---------------------------------------------------------------------------
 template <int KP, int PREC, int NW>
 __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
   constexpr int NPAIR = NB * (NB + 1) / 2;
   constexpr int NG = (NPAIR + NW - 1) / NW;
   __shared__ uint4 Xs[2][NREC][64];
-  __shared__ uint4 Pa[TP][NOUT][64];  // [TR part][output][lane]; A records in part 0
+  __shared__ uint4 Pa[TP][NOUT][64];  // [TR part][output][lane]
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -1216,6 +1216,8 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
   };
   // record index of (plane, 16-row tile, step)
   auto rec = [](int pl, int rb, int st) { return (pl * 2 + rb) * NSTEP + st; };
+  // TR part whose wave finalises output o (its slot of o holds no partial)
+  auto fin_part = [](int o) { return (o % (2 * FPW)) % TP; };
 
   f32x4 zacc[NB][4];
   f32x4 gacc[NG];
@@ -1274,37 +1276,53 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
         if (NGRP > 1 && has_next && j == SPW / 4) issue(nr0, buf ^ 1, 1);
         if (NGRP > 2 && has_next && j == SPW - 1) issue(nr0, buf ^ 1, 2);
       }
+      // Output o = 2 FPW fg + r (r = 2 f + m: feature block FPW fg + f, row
+      // tile m) is finalised by the wave of TR part r % TP in feature group
+      // fg, which keeps its own partial sum in registers; the other TR parts
+      // pass theirs through their slots.
 #pragma unroll
       for (int f = 0; f < FPW; ++f)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
-          Pa[tp][2 * (fg * FPW + f) + m][lane] =
-              make_uint4(__float_as_uint(acc[f][m][0]), __float_as_uint(acc[f][m][1]),
-                         __float_as_uint(acc[f][m][2]), __float_as_uint(acc[f][m][3]));
+          if ((2 * f + m) % TP != tp)
+            Pa[tp][2 * (fg * FPW + f) + m][lane] =
+                make_uint4(__float_as_uint(acc[f][m][0]), __float_as_uint(acc[f][m][1]),
+                           __float_as_uint(acc[f][m][2]), __float_as_uint(acc[f][m][3]));
       __syncthreads();
-      // Output o = 2 fb + m (feature block fb, row tile m): its TR parts
-      // summed in order, rounded to hi + lo and written over its TR-part-0
-      // slot as (hi pair, lo pair): lane holds A[16 m + 4 g + i][16 fb + n],
-      // half m of the A record of block fb.
-      for (int o = wave; o < NOUT; o += NW) {
-        uint4 u[TP];  // every TR part's slot read before any is used
+      // The finaliser adds the TR parts in order and rounds to hi + lo.  The A
+      // operands of block fb go to the two slots that hold no partial sum,
+      // those of outputs 2 fb (hi) and 2 fb + 1 (lo), as whole operand
+      // records: lane l's 16 bytes are its pair of row tile 0, then of row
+      // tile 1, so output 2 fb + m writes bytes 8 m .. 8 m + 7 of each lane.
 #pragma unroll
-        for (int p = 0; p < TP; ++p) u[p] = Pa[p][o][lane];
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int f = 0; f < FPW; ++f)
 #pragma unroll
-        for (int p = 0; p < TP; ++p) {
-          v[0] += __uint_as_float(u[p].x);
-          v[1] += __uint_as_float(u[p].y);
-          v[2] += __uint_as_float(u[p].z);
-          v[3] += __uint_as_float(u[p].w);
+        for (int m = 0; m < 2; ++m) {
+          if ((2 * f + m) % TP != tp) continue;
+          const int fb = fg * FPW + f, o = 2 * fb + m;
+          uint4 u[TP];  // the other TR parts' slots, read before any is used
+#pragma unroll
+          for (int p = 0; p < TP; ++p)
+            if (p != tp) u[p] = Pa[p][o][lane];
+          float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int p = 0; p < TP; ++p) {
+            if (p == tp) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] += acc[f][m][i];
+            } else {
+              v[0] += __uint_as_float(u[p].x);
+              v[1] += __uint_as_float(u[p].y);
+              v[2] += __uint_as_float(u[p].z);
+              v[3] += __uint_as_float(u[p].w);
+            }
+          }
+          uint32_t h01, l01, h23, l23;
+          split2(v[0], v[1], h01, l01);
+          split2(v[2], v[3], h23, l23);
+          ((uint2*)&Pa[fin_part(2 * fb)][2 * fb][0])[2 * lane + m] = make_uint2(h01, h23);
+          ((uint2*)&Pa[fin_part(2 * fb + 1)][2 * fb + 1][0])[2 * lane + m] = make_uint2(l01, l23);
         }
-        uint32_t h01, l01, h23, l23;
-        split2(v[0], v[1], h01, l01);
-        split2(v[2], v[3], h23, l23);
-        uint2* dst = (uint2*)&Pa[0][o][0];  // hi pairs, then lo pairs
-        dst[lane] = make_uint2(h01, h23);
-        dst[64 + lane] = make_uint2(l01, l23);
-      }
     }
     if (NGRP > 3 && has_next) issue(nr0, buf ^ 1, 3);
     // ---- part 2: Z[:, 64 w + 16 q + n] += A^T Xhat, Gram tiles
@@ -1334,17 +1352,12 @@ __global__ __launch_bounds__(NW * 64) void k_staged(FusedArgs a) {
       asm volatile("" ::: "memory");
       load_b(0, bh0, bl0);
       asm volatile("s_waitcnt lgkmcnt(%0)\n\ts_barrier" :: "n"(X2 ? 4 : 2) : "memory");
-      // A operands of block jb: the hi (lo) pairs of tiles 0 and 1 from the
-      // two outputs' slots, 8 bytes per lane each, straight into the
-      // operand's two register pairs
+      // A operands of block jb: whole operand records (hi, lo)
       uint4 ah[NB], al[NB];
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) {
-        const uint2* t0 = (const uint2*)&Pa[0][2 * jb][0];
-        const uint2* t1 = (const uint2*)&Pa[0][2 * jb + 1][0];
-        const uint2 h0 = t0[lane], h1 = t1[lane], l0 = t0[64 + lane], l1 = t1[64 + lane];
-        ah[jb] = make_uint4(h0.x, h0.y, h1.x, h1.y);
-        al[jb] = make_uint4(l0.x, l0.y, l1.x, l1.y);
+        ah[jb] = Pa[fin_part(2 * jb)][2 * jb][lane];
+        al[jb] = Pa[fin_part(2 * jb + 1)][2 * jb + 1][lane];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
