@@ -11,3 +11,6 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line(
         "markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import _progress
+    _progress.register(config.pluginmanager.getplugin("capturemanager"))

@@ -10,6 +10,7 @@ import pytest
 import oracle
 from paper_1608_04647_amd import synth
 
+from _progress import say
 from _parity import compare
 
 pytestmark = pytest.mark.gpu
@@ -26,8 +27,7 @@ def _srm():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    say(*a)
 
 
 RAGGED = synth.Workload("ragged", 5, 33, 250, 70, 7, 8)

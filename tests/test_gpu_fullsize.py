@@ -19,6 +19,7 @@ import pytest
 import oracle
 from paper_1608_04647_amd import synth
 
+from _progress import say
 from _parity import compare, proj_err
 
 pytestmark = pytest.mark.gpu
@@ -33,8 +34,7 @@ def _srm():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    say(*a)
 
 
 @pytest.mark.timeout(900)

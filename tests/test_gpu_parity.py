@@ -15,6 +15,7 @@ import pytest
 import oracle
 from paper_1608_04647_amd import synth
 
+from _progress import say
 from _parity import compare, proj_err, stored_values
 
 pytestmark = pytest.mark.gpu
@@ -31,8 +32,7 @@ def _srm():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    say(*a)
 
 
 def _run_case(name, w, prec, seed=0, n_iter=None, **kw):

@@ -12,6 +12,7 @@ import pytest
 import oracle
 from paper_1608_04647_amd import synth
 
+from _progress import say
 from _parity import compare, stored_values
 
 pytestmark = pytest.mark.gpu
@@ -28,8 +29,7 @@ def _srm():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    say(*a)
 
 
 CASES = {

@@ -9,6 +9,8 @@ import sys
 import numpy as np
 import pytest
 
+from _progress import say
+
 import oracle
 from paper_1608_04647_amd import synth
 
@@ -16,8 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    say(*a)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
