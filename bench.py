@@ -101,6 +101,24 @@ def paper_flop_model(v, t, k):
                         + 2.0 * v * k * k - 2.0 * k ** 3 / 3.0))
 
 
+def copy_stream_GBps(nbytes=4_000_000_000, reps=5):
+    """Best-of-reps rate of a plain device-to-device copy of nbytes (bytes
+    read plus bytes written, per second)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps + 1):  # the first call warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def time_fit(g, steps):
     import torch
     torch.cuda.synchronize()
@@ -309,6 +327,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the plain copy-stream rate measured after the fits")
     ap.add_argument("--cpu-subjects", type=int, default=24)
     ap.add_argument("--subjects", type=int, default=0,
                     help="development only: fewer subjects of the same shape")
@@ -443,6 +463,17 @@ def main():
         log(f"[bench] oracle check: {snap['iters']} iterations on all {w.n_subjects} subjects")
         out["error_vs_oracle"] = oracle_check(w, args.seed, snap)
         log(f"[bench] oracle check {out['error_vs_oracle']}")
+    if not args.no_stream:
+        # What a plain streaming copy reaches on this device (bytes read and
+        # written), as the practical counterpart of the 8 TB/s peak; measured
+        # after the fits, outside any timed region.
+        cs = copy_stream_GBps()
+        out["copy_stream"] = {"GBps": cs, "method": "device-to-device copy of 4 GB "
+                              "(torch), best of 5; bytes read plus bytes written"}
+        if roof["unit"] == "GB/s":
+            roof["frac_of_copy_stream"] = roof["achieved"] / cs
+            log(f"[bench] copy stream: {cs:.0f} GB/s; the dominant kernel reaches "
+                f"{100 * roof['achieved'] / cs:.0f}% of it")
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 1e9) // 4 * 4
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
