@@ -65,6 +65,10 @@ CASES = {
     "k100": synth.Workload("k100", 3, 300, 420, 150, 100, 4,
                            sigma_lo=0.5, sigma_hi=2.0, rho_lo=0.3, rho_hi=0.6),
     "k128": synth.Workload("k128", 2, 200, 260, 140, 128, 3, rho_lo=0.3, rho_hi=0.6),
+    # k = 100 over 700 TRs (ldt 704): the two-pass E-phase with a full and a
+    # partial 512-TR panel, and M-phase rounds ending in half-filled tiles
+    "k100t700": synth.Workload("k100t700", 3, 1200, 3100, 700, 100, 4,
+                               sigma_lo=0.5, sigma_hi=2.0),
     # K padding 48 (three feature blocks) through the one-pass sweep with
     # four waves (t = 180)
     "k40": synth.Workload("k40", 3, 150, 400, 180, 40, 4, sigma_lo=0.5, sigma_hi=2.0),
