@@ -2684,17 +2684,18 @@ hipError_t launch_ephase(hipStream_t st, int kp, int prec, int grid,
   return hipGetLastError();
 }
 int ephase_panel(int prec) { return prec == P_FP32 ? 256 : kEphasePanel; }
-int ereduce_ct(int kp) { return kp <= 64 ? 64 : (kp <= 96 ? 32 : 16); }
+// TRs per k_ereduce column tile: the widest whose Z tile and P_i fit LDS
+// together (FP64: KP x CT + KP x KP), so each P_i is staged by fewer
+// workgroups.
+int ereduce_ct(int kp) { return kp <= 112 ? 64 : 32; }
 hipError_t launch_ereduce(hipStream_t st, int kp, int ncol, int ngrp,
                           const RArgs& a) {
   dim3 grid(ncol, ngrp);
   switch (ereduce_ct(kp)) {
-    case 64: SRM_KP_SWITCH(kp, if constexpr (KP <= 64) hipLaunchKernelGGL(
+    case 64: SRM_KP_SWITCH(kp, if constexpr (KP <= 112) hipLaunchKernelGGL(
                  (k_ereduce<KP, 64>), grid, dim3(256), 0, st, a)); break;
-    case 32: SRM_KP_SWITCH(kp, if constexpr (KP > 64 && KP <= 96) hipLaunchKernelGGL(
+    default: SRM_KP_SWITCH(kp, if constexpr (KP > 112) hipLaunchKernelGGL(
                  (k_ereduce<KP, 32>), grid, dim3(256), 0, st, a)); break;
-    default: SRM_KP_SWITCH(kp, if constexpr (KP > 96) hipLaunchKernelGGL(
-                 (k_ereduce<KP, 16>), grid, dim3(256), 0, st, a)); break;
   }
   return hipGetLastError();
 }
