@@ -1875,35 +1875,29 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   }
   const bool warm = WARM && a.sc->polar_warm != 0;
   {
-    // Warm path: P_i = G_i^{-1/2} by the Newton-Schulz iteration
-    // X <- X + X E / 2, E = I - X G X, from the previous iteration's P_i
-    // (quadratic convergence while the Gram changes little between
-    // iterations).  It is taken when E vanishes to rounding and
+    // P_i = G_i^{-1/2} by Newton-Schulz, then certified below.  From the
+    // previous iteration's P_i: X <- X + X E / 2, E = I - X G X, quadratic
+    // while the Gram changes little between iterations.  On the first
+    // iteration, and where that start fails: the coupled form on Y = G / s, Z = I (s = |G|_F, so the
+    // spectrum of Y lies in (0, 1]): T = (3 I - Z Y) / 2, Y <- Y T,
+    // Z <- T Z, Z Y -> I and Z -> Y_0^{-1/2}, stable where the uncoupled form
+    // from a scaled identity is not.  Taken when E vanishes to rounding and
     // |X|_F^2 |G|_F < 1e13, which certifies lambda_min > 1e-13 lambda_max;
     // otherwise the Jacobi eigensolver below decides.
-    if (a.sc->polar_warm != 0 && NT == 256) {
+    if (NT == 256) {
       constexpr int RB = KP / 16;
       double* X = G + KP * LD;
       double* B = X + KP * LD;
-      const double* Pp = a.P64 + (int64_t)i * KP * KP;
-      for (int idx = tid; idx < KP * KP; idx += NT) {
-        const int p = idx / KP, q = idx % KP;
-        X[p * LD + q] = Pp[idx];
-        if (p >= m || q >= m) G[p * LD + q] = 0.0;  // zero padding up to KP
-      }
-      __syncthreads();
       const int rg = tid / 16, cg = tid % 16;
       double c[RB][RB];
-      double emax = 1.0;
-      for (int it = 0; it < 8; ++it) {
-        mm_blk<KP>(G, X, LD, k, c);  // T = G X
-        __syncthreads();
+      auto store = [&](double* M) {
 #pragma unroll
         for (int u = 0; u < RB; ++u)
 #pragma unroll
-          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
-        __syncthreads();
-        mm_blk<KP>(X, B, LD, k, c);  // X G X
+          for (int v = 0; v < RB; ++v) M[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+      };
+      // max |I - c| over the k x k entries of this thread's block
+      auto dev_from_i = [&]() {
         double em = 0.0;
 #pragma unroll
         for (int u = 0; u < RB; ++u)
@@ -1913,58 +1907,168 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
             c[u][v] = (p < k && q < k) ? (p == q ? 1.0 : 0.0) - c[u][v] : 0.0;
             em = fmax(em, fabs(c[u][v]));
           }
-        emax = block_max256(em, red);  // also orders the reads of B
-#pragma unroll
-        for (int u = 0; u < RB; ++u)
-#pragma unroll
-          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
-        __syncthreads();
-        if (emax <= 1e-14 || !(emax < 0.5)) break;
-        mm_blk<KP>(X, B, LD, k, c);  // X E
-        __syncthreads();
-        // X <- X + (X E + E X) / 4: the symmetric part of X + X E / 2
-#pragma unroll
-        for (int u = 0; u < RB; ++u)
-#pragma unroll
-          for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
-        __syncthreads();
-        for (int idx = tid; idx < KP * KP; idx += NT) {
-          const int p = idx / KP, q = idx % KP;
-          if (p < q) {
-            const double d = 0.25 * (B[p * LD + q] + B[q * LD + p]);
-            X[p * LD + q] += d;
-            X[q * LD + p] += d;
-          } else if (p == q) {
-            X[p * LD + p] += 0.5 * B[p * LD + p];
+        return em;
+      };
+      // Certifies X against G (emax = max |I - X G X|) and writes P_i;
+      // false: not taken, G unchanged.
+      auto certify = [&](double emax) {
+        // |X|_F^2, |G|_F^2 and tr(G X) = sum of the singular values of A_i
+        double nx = 0.0, ng = 0.0, tgx = 0.0;
+        for (int idx = tid; idx < k * k; idx += NT) {
+          const int p = idx / k, q = idx % k;
+          const double x = X[p * LD + q], gv = G[p * LD + q];
+          nx += x * x;
+          ng += gv * gv;
+          tgx += gv * X[q * LD + p];
+        }
+        nx = block_sum256(nx, red);
+        ng = block_sum256(ng, red);
+        tgx = block_sum256(tgx, red);
+        if (emax <= 1e-12 && nx * sqrt(ng) < 1e13) {
+          double* P = a.P64 + (int64_t)i * KP * KP;
+          for (int idx = tid; idx < KP * KP; idx += NT) {
+            const int p = idx / KP, q = idx % KP;
+            P[idx] = (p < k && q < k) ? 0.5 * (X[p * LD + q] + X[q * LD + p]) : 0.0;
           }
+          if constexpr (WARM) {
+            // No eigenvectors yet: the identity is the (orthogonal) warm start
+            // a later Jacobi solve of this subject rotates from.
+            if (a.sc->polar_warm == 0) {
+              double* Vp = a.vprev + (int64_t)i * KP * KP;
+              for (int idx = tid; idx < m * m; idx += NT)
+                Vp[(idx / m) * KP + idx % m] = (idx / m == idx % m && idx / m < k) ? 1.0 : 0.0;
+            }
+          }
+          if (tid == 0) {
+            const double t = (double)a.t;
+            if (!a.init_mode) a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
+            if (MODE == POLAR_NS) a.jac[i] = 0;
+          }
+          return true;
         }
-        __syncthreads();
-      }
-      // |X|_F^2, |G|_F^2 and tr(G X) = sum of the singular values of A_i
-      double nx = 0.0, ng = 0.0, tgx = 0.0;
-      for (int idx = tid; idx < k * k; idx += NT) {
-        const int p = idx / k, q = idx % k;
-        const double x = X[p * LD + q], gv = G[p * LD + q];
-        nx += x * x;
-        ng += gv * gv;
-        tgx += gv * X[q * LD + p];
-      }
-      nx = block_sum256(nx, red);
-      ng = block_sum256(ng, red);
-      tgx = block_sum256(tgx, red);
-      if (emax <= 1e-12 && nx * sqrt(ng) < 1e13) {
-        double* P = a.P64 + (int64_t)i * KP * KP;
+        return false;
+      };
+      bool done = false;
+      if (a.sc->polar_warm != 0) {
+        double emax = 1.0;
+        const double* Pp = a.P64 + (int64_t)i * KP * KP;
         for (int idx = tid; idx < KP * KP; idx += NT) {
           const int p = idx / KP, q = idx % KP;
-          P[idx] = (p < k && q < k) ? 0.5 * (X[p * LD + q] + X[q * LD + p]) : 0.0;
+          X[p * LD + q] = Pp[idx];
+          if (p >= m || q >= m) G[p * LD + q] = 0.0;  // zero padding up to KP
         }
-        if (tid == 0) {
-          const double t = (double)a.t;
-          if (!a.init_mode) a.rho2[i] = (a.c[i] - 2.0 * tgx + t * a.sc->tau_cur) / (t * su.v);
-          if (MODE == POLAR_NS) a.jac[i] = 0;
+        __syncthreads();
+        for (int it = 0; it < 8; ++it) {
+          mm_blk<KP>(G, X, LD, k, c);  // T = G X
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+          __syncthreads();
+          mm_blk<KP>(X, B, LD, k, c);  // X G X
+          double em = 0.0;
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int v = 0; v < RB; ++v) {
+              const int p = rg + 16 * u, q = cg + 16 * v;
+              c[u][v] = (p < k && q < k) ? (p == q ? 1.0 : 0.0) - c[u][v] : 0.0;
+              em = fmax(em, fabs(c[u][v]));
+            }
+          emax = block_max256(em, red);  // also orders the reads of B
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+          __syncthreads();
+          if (emax <= 1e-14 || !(emax < 0.5)) break;
+          mm_blk<KP>(X, B, LD, k, c);  // X E
+          __syncthreads();
+          // X <- X + (X E + E X) / 4: the symmetric part of X + X E / 2
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int v = 0; v < RB; ++v) B[(rg + 16 * u) * LD + cg + 16 * v] = c[u][v];
+          __syncthreads();
+          for (int idx = tid; idx < KP * KP; idx += NT) {
+            const int p = idx / KP, q = idx % KP;
+            if (p < q) {
+              const double d = 0.25 * (B[p * LD + q] + B[q * LD + p]);
+              X[p * LD + q] += d;
+              X[q * LD + p] += d;
+            } else if (p == q) {
+              X[p * LD + p] += 0.5 * B[p * LD + p];
+            }
+          }
+          __syncthreads();
         }
-        return;
+        done = certify(emax);
       }
+      if (!done) {  // first iteration, or the warm start failed
+        double emax = 1.0;
+        __syncthreads();  // G complete
+        double g2 = 0.0;
+        for (int idx = tid; idx < k * k; idx += NT) {
+          const double gv = G[(idx / k) * LD + idx % k];
+          g2 += gv * gv;
+        }
+        const double sc = sqrt(block_sum256(g2, red));
+        const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+        for (int idx = tid; idx < KP * KP; idx += NT) {
+          const int p = idx / KP, q = idx % KP;
+          const bool in = p < k && q < k;
+          G[p * LD + q] = in ? G[p * LD + q] * inv : 0.0;  // Y_0 (and zero padding)
+          X[p * LD + q] = (in && p == q) ? 1.0 : 0.0;      // Z_0
+        }
+        __syncthreads();
+        double prev = 1e300;
+        for (int it = 0; it < 64; ++it) {
+          mm_blk<KP>(X, G, LD, k, c);  // Z Y
+          const double em = dev_from_i();
+          const double e = block_max256(em, red);  // also orders the reads of X, G
+          if (e <= 1e-14 || !(e < 1.5) || (e < 1e-10 && e > 0.25 * prev)) break;
+          prev = e;
+          // T = (3 I - Z Y) / 2 = I + (I - Z Y) / 2
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int v = 0; v < RB; ++v) {
+              const int p = rg + 16 * u, q = cg + 16 * v;
+              c[u][v] = (p < k && q < k) ? (p == q ? 1.0 : 0.0) + 0.5 * c[u][v] : 0.0;
+            }
+          store(B);
+          __syncthreads();
+          mm_blk<KP>(G, B, LD, k, c);  // Y T
+          __syncthreads();
+          store(G);
+          mm_blk<KP>(B, X, LD, k, c);  // T Z
+          __syncthreads();
+          store(X);
+          __syncthreads();
+        }
+        // X = Z / sqrt(s) = G^{-1/2}; G again from the slices (Y overwrote it)
+        const double xs = sc > 0.0 ? 1.0 / sqrt(sc) : 0.0;
+        for (int idx = tid; idx < KP * KP; idx += NT) {
+          const int p = idx / KP, q = idx % KP;
+          X[p * LD + q] *= xs;
+          double gv = 0.0;
+          if (p < k && q < k) {
+            const int r = p <= q ? p : q, cc = p <= q ? q : p;
+            for (int sl = su.s_beg; sl < su.s_end; ++sl)
+              gv += (double)a.gpart[(int64_t)sl * KP * KP + r * KP + cc];
+          }
+          G[p * LD + q] = gv;
+        }
+        __syncthreads();
+        mm_blk<KP>(G, X, LD, k, c);  // G X
+        store(B);
+        __syncthreads();
+        mm_blk<KP>(X, B, LD, k, c);  // X G X
+        emax = block_max256(dev_from_i(), red);
+        done = certify(emax);
+      }
+      if (done) return;
       __syncthreads();  // not taken: G is unchanged; the eigensolver decides
     }
   }
