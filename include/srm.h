@@ -206,7 +206,8 @@ srm_status srm_fit(srm_ctx *ctx, int32_t n_iter, double *loglik);
  *  SRM_PHASE_MPHASE    A = Xhat S^T over all subjects (Eq. 4, A_i)
  *  SRM_PHASE_EPHASE    per-slice A^T Xhat and A^T A (Eq. 10 partials, Eq. 4 Gram)
  *  SRM_PHASE_POLAR     per-subject FP64 polar factor (Newton-Schulz from the
- *                      previous one, else Jacobi) and rho_i^2 (Eq. 4-5)
+ *                      previous one or from G_i / |G_i|_F, else Jacobi) and
+ *                      rho_i^2 (Eq. 4-5)
  *  SRM_PHASE_EREDUCE   Y = sum_i rho_i^-2 W_i^T Xhat_i (Eq. 10 reduction)
  *  SRM_PHASE_POSTERIOR k x k posterior, S, Sigma_s, log-likelihood (Eq. 7-11)
  *  SRM_PHASE_FUSED     one-pass sweep forming A, A^T Xhat and A^T A together
@@ -352,8 +353,9 @@ srm_status srm_get_info(const srm_ctx *ctx, srm_info *info);
  *                 query *count; at most capacity are written).
  * srm_autotune:   times candidates (one warm-up and `trials` iterations each,
  *                 direct launches, HIP events around the phases the shapes
- *                 change: the sweep kernels and the E-step reduction, not the
- *                 polar and posterior steps) by coordinate search (the sweep's
+ *                 change: the sweep kernels, the E-step reduction and the
+ *                 posterior, which reads one reduction partial per subject
+ *                 group; not the polar step) by coordinate search (the sweep's
  *                 shapes, then the reduction's), starting from the shapes in
  *                 use, which a candidate replaces only when it is more than 1%
  *                 faster; restores the carried state after every trial, puts

@@ -787,8 +787,10 @@ srm_status time_tuning(srm_ctx* c, const srm_tuning& t, int trials, double* ms, 
     c->profiling = false;
     HIP_OR_FAIL(e);
     HIP_OR_FAIL(hipStreamSynchronize(c->stream));
+    // The posterior reads one partial of the reduction per subject group, so
+    // the reduction's shape changes its time as well.
     for (int ph : {SRM_PHASE_MPHASE, SRM_PHASE_EPHASE, SRM_PHASE_FUSED, SRM_PHASE_GRAM,
-                   SRM_PHASE_EREDUCE}) {
+                   SRM_PHASE_EREDUCE, SRM_PHASE_POSTERIOR}) {
       if (!c->recorded[ph]) continue;
       float f = 0.f;
       HIP_OR_FAIL(hipEventElapsedTime(&f, c->ev[2 * ph], c->ev[2 * ph + 1]));
