@@ -831,7 +831,9 @@ std::string tune_key(const srm_ctx* c) {
   for (auto& ch : arch)
     if (ch == '\t' || ch == ' ' || ch == '\n') ch = '_';
   char buf[256];
-  snprintf(buf, sizeof buf, "%s/%dcu prec=%d kp=%d ldt=%lld sweep=%d n=%d rows=%lld",
+  // "trial=2": trials time the posterior too; entries timed without it are
+  // not reused.
+  snprintf(buf, sizeof buf, "trial=2 %s/%dcu prec=%d kp=%d ldt=%lld sweep=%d n=%d rows=%lld",
            arch.c_str(), ncu, p.prec, p.KP, (long long)p.ldt,
            p.gram ? 2 : (p.fused ? 0 : 1), p.N, (long long)p.total_rows);
   return std::string(buf);
