@@ -1843,9 +1843,12 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
   constexpr bool WARM = KP <= 80;
   constexpr bool IN_LDS = KP <= 80;
   constexpr bool G_LDS = IN_LDS || MODE == POLAR_JAC;
+  // Above 80, the Newton-Schulz launch keeps its iterate X in LDS (read by
+  // every product of a step), G and B in global scratch.
+  constexpr bool X_LDS = !IN_LDS && MODE == POLAR_NS;
   constexpr int MAXP = (KP + 1) / 2;
   constexpr int NE = (KP * KP + NT - 1) / NT;  // product entries per thread
-  __shared__ double lds[IN_LDS ? 3 * KP * LD : (G_LDS ? KP * LD : 1)];
+  __shared__ double lds[IN_LDS ? 3 * KP * LD : (G_LDS || X_LDS ? KP * LD : 1)];
   __shared__ double cs_[MAXP], sn_[MAXP];
   __shared__ double red[4];
   __shared__ int pp_[MAXP], qq_[MAXP];
@@ -1886,8 +1889,8 @@ __global__ __launch_bounds__(NT) void k_polar(QArgs a) {
     // otherwise the Jacobi eigensolver below decides.
     if (NT == 256) {
       constexpr int RB = KP / 16;
-      double* X = G + KP * LD;
-      double* B = X + KP * LD;
+      double* X = X_LDS ? lds : G + KP * LD;
+      double* B = G + 2 * KP * LD;
       const int rg = tid / 16, cg = tid % 16;
       double c[RB][RB];
       auto store = [&](double* M) {
