@@ -201,6 +201,12 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
         tuning.update(chosen=best, autotune_ms_per_iter=best_ms,
                       autotune_s=time.perf_counter() - t0)
         log(f"[bench] autotuned {prec}: {best} ({best_ms:.3f} ms/iter in its trials)")
+    # the first iteration of the fit, phase by phase (its polar step has no
+    # previous P_i to start from), then the state it started from again
+    st0 = g.get_state()
+    first_ph = g.profile(1)
+    g.set_state(st0)
+    log(f"[bench] first iteration ({prec}): polar {first_ph.get('polar', 0.0):.3f} ms")
     log(f"[bench] init {prec} done in {init_s:.2f}s; warmup {warmup}")
     if warmup:
         g.fit(warmup)
@@ -240,7 +246,8 @@ def run_form(srm, X, W0, w, v, prec, steps, warmup, prof_steps, gram=False, tune
            "tuning": tuning, "ingest": ingest,
            "sweep": info["sweep"], "graph_replayed": info["graph"],
            "hbm_GBps": alg["iter_bytes"] / (dt / steps) / 1e9,
-           "phase_ms": ph, "alg": alg, "ll_last": float(ll[-1]) if len(ll) else None}
+           "phase_ms": ph, "first_iteration_phase_ms": first_ph, "alg": alg,
+           "ll_last": float(ll[-1]) if len(ll) else None}
     return g, res
 
 
@@ -428,6 +435,7 @@ def main():
            "hbm_GBps": head["hbm_GBps"],
            "hbm_frac": head["hbm_GBps"] / HBM_PEAK_GBS,
            "phase_ms": ph,
+           "first_iteration_phase_ms": head["first_iteration_phase_ms"],
            "tuning": head["tuning"],
            "sweep": head["sweep"], "graph_replayed": head["graph_replayed"],
            "paper_model_GFLOPs": paper_flop_model(v, w.t, w.k) / (head["ms_per_step"] / 1e3) / 1e9,
